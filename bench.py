@@ -1,0 +1,195 @@
+"""Benchmark of the CPRA hot path on one MI355X.
+
+One step = one whole reconstruction of the 512x512x360 cell-like scan
+(N = 512, Np = 360) with inputs already resident in HBM: plan set-up, input
+preparation and random initial objects (submit), 200 HIO iterations with
+the carousel coupling every 10 iterations, and step D (Fourier-slice
+insertion + 3D inverse FFT into a 512^3 volume).  The headline value is
+pattern-iterations/s over the whole step: 200 * 360 / step time.
+
+Also reported:
+  * roofline of the dominant kernel (HIP events around every column and row
+    pass on the plan's stream, algorithmic bytes per launch / mean duration);
+  * cpu_baseline: the FP64 oracle on a bounded sample (8 angles x 3
+    iterations, single thread) on this machine's host;
+  * per-step latency percentiles (submit to volume).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+N, NP, ITERS, N_EI, BETA = 512, 360, 200, 10, 0.9
+
+
+def algorithmic_bytes(N, Np, n_ei, amp_bytes=8, real_bytes=4):
+    """Bytes each pass must move per launch, averaged over an episode.
+
+    Column pass per angle: read P and write Pmid (N x N/2 complex each) and
+    read the amplitude pairs (N x N/2 pairs); at an episode boundary it also
+    reads the two neighbours' P.  Row pass per angle: read Pmid, read and
+    write the real iterate g, write P, read the support bits; at a boundary
+    it also reads the two neighbours' g.
+    """
+    H = N // 2
+    cplane = N * H * 2 * real_bytes
+    rplane = N * N * real_bytes
+    col = 2 * cplane + N * H * amp_bytes + (2 * cplane) / n_ei
+    row = 2 * cplane + 2 * rplane + N * N / 8 + (2 * rplane) / n_ei
+    return col * Np, row * Np
+
+
+def cpu_baseline(scan, threads=1):
+    """Time the FP64 oracle on 8 angles x 3 iterations in a single-threaded child process."""
+    import tempfile
+    sample = 8
+    with tempfile.TemporaryDirectory() as td:
+        np.save(os.path.join(td, "I.npy"), scan["I"][:sample])
+        np.save(os.path.join(td, "S.npy"), scan["support"][:sample])
+        code = f"""
+import sys, time, json, numpy as np
+sys.path.insert(0, {ROOT!r})
+from oracle import cpra as C
+I = np.load({os.path.join(td, 'I.npy')!r}); S = np.load({os.path.join(td, 'S.npy')!r})
+o = C.Oracle({N}, {NP}, seed={scan['phase_seed']}, n_ei={N_EI})
+t0 = time.perf_counter()
+o.submit(0, I, S)
+t1 = time.perf_counter()
+o.iterate(3, C.HIO, {BETA})
+t2 = time.perf_counter()
+print(json.dumps({{"submit_s": t1 - t0, "iter_s": t2 - t1}}))
+"""
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads), OPENBLAS_NUM_THREADS=str(threads),
+                   MKL_NUM_THREADS=str(threads), NUMEXPR_NUM_THREADS=str(threads), HIP_VISIBLE_DEVICES="",
+                   CUDA_VISIBLE_DEVICES="", ROCR_VISIBLE_DEVICES="")
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+        if out.returncode != 0:
+            return {"error": out.stderr[-500:]}
+        r = json.loads(out.stdout.strip().splitlines()[-1])
+    pit = sample * 3 / r["iter_s"]
+    return {"value": pit, "unit": "pattern-iterations/s", "cores": threads, "kind": "oracle",
+            "sample": f"N=512 cell scan, angles 0-7 (all present, so the 8 form the coupling ring), "
+                      f"3 HIO iterations incl. one coupling; FP64 numpy oracle, 1 thread; "
+                      f"{r['iter_s']:.1f} s iterate + {r['submit_s']:.1f} s submit"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--amp16", action="store_true", help="FP16 amplitude storage")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--iters", type=int, default=ITERS)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU (multi-GPU sharding is a design note only); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2402_05283_amd as cp
+    from synth import make_scan
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    print(f"[bench] generating the N={N} Np={NP} scan", file=sys.stderr, flush=True)
+    t = time.time()
+    scan = make_scan(4)
+    print(f"[bench] scan ready in {time.time() - t:.1f} s", file=sys.stderr, flush=True)
+    I = torch.from_numpy(scan["I"]).to(dev)
+    S = torch.from_numpy(scan["support"]).to(dev)
+    vol = torch.empty((N, N, N), dtype=torch.float32, device=dev)
+    amp = cp.AMP_F16 if args.amp16 else cp.AMP_F32
+    stream = torch.cuda.current_stream(dev)
+
+    col_ms = row_ms = 0.0
+    col_n = row_n = 0
+    lat = []
+
+    def one_step(timed):
+        nonlocal col_ms, row_ms, col_n, row_n
+        t0 = time.perf_counter()
+        plan = cp.Plan(N, NP, n_ei=N_EI, amp=amp, seed=scan["phase_seed"], stream=stream)
+        if timed:
+            plan.set_kernel_timing(True)
+        plan.submit(0, I, S)
+        plan.iterate(args.iters, cp.HIO, BETA)
+        plan.assemble_volume(vol)
+        if timed:
+            c, cn, r, rn = plan.kernel_timing()
+            col_ms += c; row_ms += r; col_n += cn; row_n += rn
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    for i in range(args.warmup):
+        one_step(False)
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        lat.append(one_step(True))
+        print(f"[bench] step {i + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms_per_step = total / args.steps * 1e3
+    value = args.iters * NP * args.steps / total
+
+    col_b, row_b = algorithmic_bytes(N, NP, N_EI, amp_bytes=4 if args.amp16 else 8)
+    col_avg = col_ms / max(col_n, 1)
+    row_avg = row_ms / max(row_n, 1)
+    col_gbs = col_b / (col_avg * 1e-3) / 1e9
+    row_gbs = row_b / (row_avg * 1e-3) / 1e9
+    dom = ("k_col", col_avg, col_gbs, col_b) if col_avg >= row_avg else ("k_row", row_avg, row_gbs, row_b)
+    roofline = {"bound": "hbm", "achieved": round(dom[2], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dom[2] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom[0],
+                "avg_launch_ms": round(dom[1], 5), "bytes_per_launch": int(dom[3]),
+                "other": {"kernel": "k_row" if dom[0] == "k_col" else "k_col",
+                          "avg_launch_ms": round(row_avg if dom[0] == "k_col" else col_avg, 5),
+                          "achieved": round(row_gbs if dom[0] == "k_col" else col_gbs, 1)}}
+    iter_ms = (col_ms + row_ms) / max(col_n, 1)
+    out = {
+        "metric": "pattern-iterations/s at N=512,N_p=360 + p99 last-frame-to-volume latency",
+        "value": round(value, 1),
+        "unit": "pattern-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" + ("+f16amp" if args.amp16 else ""),
+        "data": "synthetic",
+        "config": {"workload": "cell-like 512^3 object, N=512, N_p=360, 200 HIO iterations "
+                               "(beta 0.9, carousel every 10), prep + init + step D, one scan per step",
+                   "N": N, "N_p": NP, "iterations": args.iters, "n_ei": N_EI},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                       "what": "submit-to-volume time of a whole scan handed over at once"},
+        "iteration_only": {"ms_per_iteration": round(iter_ms, 4),
+                           "pattern_iterations_per_s": round(NP / (iter_ms * 1e-3), 1)},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(scan)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * cpra.h - C ABI of the carousel phase retrieval (CPRA) hot path on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: F. Ai, V. Lomakin, O. Shpyrko, "Real time 3D coherent X-ray
+ * diffraction imaging" (arXiv 2402.05283).  A scan is N_p intensity maps
+ * I(q_t,n, q_i,n) of N x N pixels, one per rotation angle theta_n about z
+ * (problem statement, Eq. 1-3).  Each map is phased by 2D iterative phase
+ * retrieval of its projected object (PO); the POs of neighbouring angles
+ * are re-combined at the start of every episode (Eq. 4, the "carousel");
+ * the retrieved 2D spectra are finally inserted along their Fourier slices
+ * into a 3D spectrum and transformed back (step D).
+ *
+ * Conventions shared by every entry point:
+ *   - Real-space arrays (supports, POs) are [n][z][t] with z the rotation
+ *     axis, t the transverse axis, origin at index N/2 (centred).
+ *   - Intensities are [n][w][u] with zero frequency at index N/2 (centred),
+ *     w the frequency along z and u along t.  I < 0 marks an unmeasured
+ *     pixel (beamstop); NaN or Inf is rejected.
+ *   - The output volume is [z][y][x], origin at index N/2.
+ *   - All calls return a cpra_status and never throw or abort.  An argument
+ *     error leaves the plan unchanged.  A device error poisons the plan:
+ *     every later call on it returns CPRA_ERR_STATE (cpra_destroy excepted).
+ *   - One host thread per plan at a time; distinct plans are independent.
+ */
+#ifndef CPRA_H
+#define CPRA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cpra_plan_s* cpra_plan_t;
+
+typedef enum {
+  CPRA_OK = 0,
+  CPRA_ERR_ARG = -1,          /* invalid argument; nothing changed            */
+  CPRA_ERR_OOM = -2,          /* workspace too small                          */
+  CPRA_ERR_DEVICE = -3,       /* HIP runtime error; the plan is now poisoned  */
+  CPRA_ERR_STATE = -4,        /* call not valid in the plan's current state   */
+  CPRA_ERR_UNSUPPORTED = -5,  /* size or option not built                     */
+  CPRA_ERR_DATA = -6          /* NaN or Inf in the intensities                */
+} cpra_status;
+
+enum { CPRA_HIO = 0, CPRA_ER = 1 };                  /* real-space update     */
+enum { CPRA_WRAP_MIRROR = 0, CPRA_WRAP_PLAIN = 1 };  /* carousel seam rule    */
+enum { CPRA_REAL_F32 = 0, CPRA_REAL_F64 = 1 };       /* arithmetic precision  */
+enum { CPRA_AMP_F32 = 0, CPRA_AMP_F16 = 1 };         /* amplitude storage     */
+enum { CPRA_PTR_HOST = 0, CPRA_PTR_DEVICE = 1 };
+
+typedef struct {
+  uint32_t struct_size;  /* = sizeof(cpra_params)                                     */
+  int32_t N;             /* map side; 64, 128, 256, 512 or 1024 (else UNSUPPORTED)      */
+  int32_t Np;            /* number of angles, >= 1                                      */
+  const double* theta;   /* Np angles in radians (host, copied), or NULL: pi*n/Np       */
+  double alpha[3];       /* Eq. 4 weights a_-1, a_0, a_+1; each >= 0, |sum - 1| <= 1e-12 */
+  int32_t n_ei;          /* iterations per episode (coupling period), >= 1              */
+  int32_t wrap;          /* CPRA_WRAP_MIRROR: the neighbour reached across the 180-deg
+                            seam is t-mirrored (PO at theta+pi); CPRA_WRAP_PLAIN: not   */
+  int32_t positivity;    /* 1: the object constraint is support AND (g' >= 0)           */
+  int32_t real_type;     /* CPRA_REAL_F32 (product path) or CPRA_REAL_F64               */
+  int32_t amp_type;      /* CPRA_AMP_F32, or CPRA_AMP_F16 (F32 plans only): sqrt(I) kept
+                            as binary16 times a per-angle power-of-two scale            */
+  uint64_t seed;         /* key of the counter-based SplitMix64 initial phases          */
+} cpra_params;
+
+/*
+ * Device workspace bytes a plan with these parameters needs (host only; no
+ * GPU call).  ERR_ARG / ERR_UNSUPPORTED for invalid or unbuilt parameters.
+ */
+cpra_status cpra_workspace_size(const cpra_params* params, size_t* bytes);
+
+/*
+ * Create a plan on the current HIP device.  `workspace` is caller-owned
+ * device memory of at least cpra_workspace_size() bytes, 256-byte aligned,
+ * that must outlive the plan; `hip_stream` (hipStream_t, NULL = default
+ * stream) orders all of the plan's device work.  The plan owns only host
+ * memory.  Twiddle tables are generated on the device in FP64.
+ */
+cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t workspace_bytes,
+                             void* hip_stream, cpra_plan_t* out);
+
+/*
+ * Input preparation (problem statement; step A initialisation): hand over
+ * the maps of angles [first, first+count).  intensity: count x N x N float,
+ * centred [n][w][u]; support: count x N x N uint8 (nonzero = inside),
+ * centred [n][z][t].  Both on the host (CPRA_PTR_HOST: copied before the
+ * call returns) or on the device (CPRA_PTR_DEVICE: read in stream order).
+ * Computes A = sqrt(I), packs the support, and draws each angle's random
+ * initial PO (W_0): Re F2^-1(A exp(i phi)), phi from SplitMix64(seed) at
+ * counter (n*N + w)*N + u.  An angle may be submitted once.  An angle that
+ * arrives mid-episode waits and joins at the next episode boundary.
+ * Synchronises the stream (to report ERR_DATA).
+ */
+cpra_status cpra_submit_angles(cpra_plan_t plan, int32_t first, int32_t count,
+                               const float* intensity, const uint8_t* support, int32_t ptr_kind);
+
+/*
+ * Run n_iter iterations over the angles present (steps B, Eq. 4).  At each
+ * episode boundary (global iteration count k with k mod n_ei == 0) every
+ * present PO is replaced by a_-1 X_{n-1} + a_0 X_n + a_+1 X_{n+1}, X the
+ * previous episode's objects, over the periodic ring of present angles
+ * (absent neighbours drop out, weights renormalised).  Each iteration:
+ * G = F2(g); E_F = sqrt(sum (|G|-A)^2 / sum A^2) over measured pixels;
+ * G' = A G/|G|; g' = Re F2^-1(G'); gamma = support AND (g' >= 0);
+ * HIO (algo CPRA_HIO): g <- g' on gamma, g - beta g' elsewhere;
+ * ER (CPRA_ER): g <- g' on gamma, 0 elsewhere.  The last iteration of an
+ * episode writes the estimate g' on gamma, 0 elsewhere.
+ * err_out: NULL, or host n_iter x Np doubles receiving E_F (NaN for absent
+ * angles); non-NULL synchronises the stream.  Otherwise asynchronous.
+ * ERR_STATE if no angle is present.
+ */
+cpra_status cpra_iterate(cpra_plan_t plan, int32_t n_iter, int32_t algo, double beta, double* err_out);
+
+/*
+ * Current real-space iterate of every angle, Np x N x N [n][z][t] centred,
+ * float (F32 plans) or double (F64 plans), host or device.  At an episode
+ * end this is the episode's estimate.  Host copies synchronise the stream.
+ */
+cpra_status cpra_read_objects(cpra_plan_t plan, void* out, int32_t ptr_kind);
+
+/*
+ * Warm start: replace the current iterate of every submitted angle by
+ * `objects` (Np x N x N [n][z][t] centred, float for F32 plans or double for
+ * F64 plans; host or device; rows of angles not yet submitted are ignored)
+ * and recompute the plan's internal row spectra from it.  The iteration
+ * count k is unchanged, so the next episode boundary couples these objects.
+ * Lets a caller seed a scan from an earlier result or from a separate
+ * pre-reconstruction.  Synchronises the stream.
+ */
+cpra_status cpra_load_objects(cpra_plan_t plan, const void* objects, int32_t ptr_kind);
+
+/*
+ * Step D: insert the spectra F2(O'_n) of the current estimates along their
+ * Fourier slices (nearest voxel of (-u sin t, u cos t, w), floor(x+0.5) in
+ * FP64, averaged per voxel, empty voxels zero) and return the real part of
+ * the 3D inverse transform: N x N x N [z][y][x] centred, float (F32 plans)
+ * or double (F64 plans), device memory.  Computed z-plane by z-plane (the
+ * 3D transform factorises into the row spectra already held per angle), so
+ * no N^3 complex grid is formed.  ERR_STATE unless k mod n_ei == 0 and k > 0.
+ */
+cpra_status cpra_assemble_volume(cpra_plan_t plan, void* d_volume);
+
+/* Free the plan's host memory.  The workspace stays the caller's. */
+cpra_status cpra_destroy(cpra_plan_t plan);
+
+/* Last error message of the plan (or of the last failed create if plan is NULL). */
+const char* cpra_last_error(cpra_plan_t plan);
+
+/* Global iteration count k of the plan (host only). */
+cpra_status cpra_iteration_count(cpra_plan_t plan, int64_t* k);
+
+/*
+ * Measurement: enable (1) or disable (0) HIP-event timing of every column
+ * and row pass the plan launches (one event before, between and after the
+ * two passes of each iteration, on the plan's stream).  Enabling resets the
+ * accumulated times.
+ */
+cpra_status cpra_set_kernel_timing(cpra_plan_t plan, int32_t enable);
+
+/*
+ * Summed device time (ms) and launch counts of the column and row passes
+ * recorded since timing was enabled or last read; synchronises the stream
+ * and resets the accumulators.
+ */
+cpra_status cpra_kernel_timing(cpra_plan_t plan, double* col_ms, int64_t* col_launches, double* row_ms,
+                               int64_t* row_launches);
+
+/*
+ * Host-only geometry of step D (no GPU call), for checking: for every angle
+ * n and centred frequency index iu (u = iu - N/2) the native voxel indices
+ * kx = floor(-u sin(theta_n) + 0.5) mod N and ky = floor(u cos(theta_n) + 0.5)
+ * mod N.  kx_out, ky_out: host Np x N int32.  theta NULL: pi*n/Np.
+ */
+cpra_status cpra_slice_cells(int32_t N, int32_t Np, const double* theta, int32_t* kx_out, int32_t* ky_out);
+
+/*
+ * Host-only coupling table (no GPU call): for each angle, the neighbour
+ * indices, rescaled weights and seam-mirror flags used at an episode
+ * boundary, given which angles are present (uint8 Np, NULL = all).
+ * left/right: int32 Np; w: double Np x 3 (a_-1, a_0, a_+1 after
+ * renormalisation); mirror: uint8 Np x 2 (left, right).
+ */
+cpra_status cpra_coupling_table(const cpra_params* params, const uint8_t* present, int32_t* left,
+                                int32_t* right, double* w, uint8_t* mirror);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPRA_H */

@@ -153,6 +153,10 @@ class Oracle:
         self.A = np.zeros((Np, N, N))
         self.S = np.zeros((Np, N, N), dtype=bool)
         self.g = np.zeros((Np, N, N))
+        # kept for tests: the iterate entering and the g' of the last iteration
+        # (a pixel with g' within rounding of 0 may take either HIO branch)
+        self.g_prev = np.zeros((Np, N, N))
+        self.last_gp = np.zeros((Np, N, N))
         self.landed = np.zeros(Np, dtype=bool)
         self.present = np.zeros(Np, dtype=bool)
         self.k = 0
@@ -169,7 +173,7 @@ class Oracle:
         if self.k % self.n_ei == 0:
             self.present = self.landed.copy()
 
-    def iterate(self, n_iter, algo=HIO, beta=0.9, angles=None):
+    def iterate(self, n_iter, algo=HIO, beta=0.9):
         """Run n_iter iterations over the present angles; returns E_F history (n_iter, Np)."""
         err = np.full((n_iter, self.Np), np.nan)
         for i in range(n_iter):
@@ -181,6 +185,8 @@ class Oracle:
                 G = forward(self.g[n])
                 err[i, n] = fourier_error(G, self.A[n])
                 gp = inverse_real(modulus_projection(G, self.A[n]))
+                self.g_prev[n] = self.g[n]
+                self.last_gp[n] = gp
                 self.g[n] = real_space_update(self.g[n], gp, self.S[n], algo, beta, self.positivity, estimate)
             self.k += 1
         return err

@@ -1,0 +1,240 @@
+"""ctypes binding of libcpra.so (argument marshalling only).
+
+Every step of the hot path runs in the library's HIP kernels; PyTorch is
+used here only to own device memory (the plan workspace, inputs, outputs)
+and to supply the HIP stream.  There is no CPU fallback: if the library is
+missing, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcpra.so")
+
+CPRA_OK = 0
+STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_OOM", -3: "ERR_DEVICE", -4: "ERR_STATE", -5: "ERR_UNSUPPORTED",
+          -6: "ERR_DATA"}
+HIO, ER = 0, 1
+WRAP_MIRROR, WRAP_PLAIN = 0, 1
+REAL_F32, REAL_F64 = 0, 1
+AMP_F32, AMP_F16 = 0, 1
+PTR_HOST, PTR_DEVICE = 0, 1
+
+EXPORTED = [
+    "cpra_workspace_size", "cpra_plan_create", "cpra_submit_angles", "cpra_iterate", "cpra_read_objects",
+    "cpra_assemble_volume", "cpra_destroy", "cpra_last_error", "cpra_iteration_count", "cpra_slice_cells",
+    "cpra_coupling_table", "cpra_set_kernel_timing", "cpra_kernel_timing", "cpra_load_objects",
+]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("N", ctypes.c_int32),
+        ("Np", ctypes.c_int32),
+        ("theta", ctypes.POINTER(ctypes.c_double)),
+        ("alpha", ctypes.c_double * 3),
+        ("n_ei", ctypes.c_int32),
+        ("wrap", ctypes.c_int32),
+        ("positivity", ctypes.c_int32),
+        ("real_type", ctypes.c_int32),
+        ("amp_type", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class CpraError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libcpra.so (built in-tree by paper_2402_05283_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2402_05283_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    c = ctypes
+    P = c.POINTER
+    lib.cpra_workspace_size.argtypes = [P(Params), P(c.c_size_t)]
+    lib.cpra_plan_create.argtypes = [P(Params), c.c_void_p, c.c_size_t, c.c_void_p, P(c.c_void_p)]
+    lib.cpra_submit_angles.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_void_p, c.c_void_p, c.c_int32]
+    lib.cpra_iterate.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_double, c.c_void_p]
+    lib.cpra_read_objects.argtypes = [c.c_void_p, c.c_void_p, c.c_int32]
+    lib.cpra_assemble_volume.argtypes = [c.c_void_p, c.c_void_p]
+    lib.cpra_destroy.argtypes = [c.c_void_p]
+    lib.cpra_last_error.argtypes = [c.c_void_p]
+    lib.cpra_last_error.restype = c.c_char_p
+    lib.cpra_iteration_count.argtypes = [c.c_void_p, P(c.c_int64)]
+    lib.cpra_slice_cells.argtypes = [c.c_int32, c.c_int32, c.c_void_p, c.c_void_p, c.c_void_p]
+    lib.cpra_coupling_table.argtypes = [P(Params), c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p]
+    lib.cpra_load_objects.argtypes = [c.c_void_p, c.c_void_p, c.c_int32]
+    lib.cpra_set_kernel_timing.argtypes = [c.c_void_p, c.c_int32]
+    lib.cpra_kernel_timing.argtypes = [c.c_void_p, P(c.c_double), P(c.c_int64), P(c.c_double), P(c.c_int64)]
+    for name in EXPORTED:
+        if name != "cpra_last_error":
+            getattr(lib, name).restype = c.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st, plan=None):
+    if st != CPRA_OK:
+        msg = load().cpra_last_error(plan)
+        raise CpraError(st, msg.decode() if msg else "")
+
+
+def make_params(N, Np, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=WRAP_MIRROR, positivity=True,
+                real=REAL_F32, amp=AMP_F32, seed=0):
+    p = Params()
+    p.struct_size = ctypes.sizeof(Params)
+    p.N, p.Np = int(N), int(Np)
+    p._theta_keep = None
+    if theta is not None:
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        p._theta_keep = th
+        p.theta = th.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for i in range(3):
+        p.alpha[i] = float(alpha[i])
+    p.n_ei, p.wrap, p.positivity = int(n_ei), int(wrap), int(bool(positivity))
+    p.real_type, p.amp_type = int(real), int(amp)
+    p.seed = int(seed) % (1 << 64)
+    return p
+
+
+def workspace_size(params) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().cpra_workspace_size(ctypes.byref(params), ctypes.byref(n)))
+    return n.value
+
+
+def slice_cells(N, Np, theta=None):
+    kx = np.zeros((Np, N), np.int32)
+    ky = np.zeros((Np, N), np.int32)
+    th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+    _check(load().cpra_slice_cells(N, Np, None if th is None else th.ctypes.data, kx.ctypes.data, ky.ctypes.data))
+    return kx, ky
+
+
+def coupling_table(params, present=None):
+    Np = params.Np
+    left = np.zeros(Np, np.int32)
+    right = np.zeros(Np, np.int32)
+    w = np.zeros((Np, 3), np.float64)
+    mirror = np.zeros((Np, 2), np.uint8)
+    pr = None if present is None else np.ascontiguousarray(present, dtype=np.uint8)
+    _check(load().cpra_coupling_table(ctypes.byref(params), None if pr is None else pr.ctypes.data, left.ctypes.data,
+                                      right.ctypes.data, w.ctypes.data, mirror.ctypes.data))
+    return left, right, w, mirror
+
+
+class Plan:
+    """One scan on the current device: owns a torch workspace tensor and a library plan."""
+
+    def __init__(self, N, Np, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=WRAP_MIRROR, positivity=True,
+                 real=REAL_F32, amp=AMP_F32, seed=0, stream=None, device=None):
+        import torch
+        self.torch = torch
+        lib = load()
+        self.params = make_params(N, Np, theta, alpha, n_ei, wrap, positivity, real, amp, seed)
+        self.N, self.Np = int(N), int(Np)
+        self.real = real
+        self.dtype = torch.float64 if real == REAL_F64 else torch.float32
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        nbytes = workspace_size(self.params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        handle = ctypes.c_void_p(0)
+        st = lib.cpra_plan_create(ctypes.byref(self.params), ctypes.c_void_p(self._ws_ptr), nbytes,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle))
+        _check(st, None)
+        self.handle = handle
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            load().cpra_destroy(h)
+            self.handle = None
+
+    def submit(self, first, intensity, support):
+        """intensity: (count,N,N) float32; support: (count,N,N) uint8 — torch CUDA tensors or numpy arrays."""
+        torch = self.torch
+        if isinstance(intensity, np.ndarray):
+            I = np.ascontiguousarray(intensity, dtype=np.float32)
+            S = np.ascontiguousarray(support, dtype=np.uint8)
+            count = I.shape[0]
+            st = load().cpra_submit_angles(self.handle, first, count, I.ctypes.data, S.ctypes.data, PTR_HOST)
+        else:
+            I = intensity.contiguous()
+            S = support.contiguous()
+            if I.dtype != torch.float32 or S.dtype != torch.uint8 or not I.is_cuda or not S.is_cuda:
+                raise TypeError("device inputs must be CUDA float32 intensity and uint8 support")
+            count = I.shape[0]
+            st = load().cpra_submit_angles(self.handle, first, count, ctypes.c_void_p(I.data_ptr()),
+                                           ctypes.c_void_p(S.data_ptr()), PTR_DEVICE)
+        _check(st, self.handle)
+
+    def iterate(self, n_iter, algo=HIO, beta=0.9, errors=False):
+        err = np.zeros((n_iter, self.Np), np.float64) if errors else None
+        st = load().cpra_iterate(self.handle, int(n_iter), int(algo), float(beta),
+                                 None if err is None else err.ctypes.data)
+        _check(st, self.handle)
+        return err
+
+    def objects(self, out=None):
+        torch = self.torch
+        if out is None:
+            out = torch.empty((self.Np, self.N, self.N), dtype=self.dtype, device=self.device)
+        _check(load().cpra_read_objects(self.handle, ctypes.c_void_p(out.data_ptr()), PTR_DEVICE), self.handle)
+        return out
+
+    def load_objects(self, objects):
+        """Warm start: set the current iterate of every submitted angle (torch CUDA tensor or numpy array)."""
+        torch = self.torch
+        if isinstance(objects, np.ndarray):
+            a = np.ascontiguousarray(objects, dtype=np.float64 if self.real == REAL_F64 else np.float32)
+            if a.shape != (self.Np, self.N, self.N):
+                raise ValueError("objects must be (Np, N, N)")
+            st = load().cpra_load_objects(self.handle, a.ctypes.data, PTR_HOST)
+        else:
+            a = objects.contiguous()
+            if a.dtype != self.dtype or tuple(a.shape) != (self.Np, self.N, self.N) or not a.is_cuda:
+                raise TypeError("objects must be a CUDA tensor of shape (Np, N, N) in the plan's precision")
+            st = load().cpra_load_objects(self.handle, ctypes.c_void_p(a.data_ptr()), PTR_DEVICE)
+        _check(st, self.handle)
+
+    def assemble_volume(self, out=None):
+        torch = self.torch
+        if out is None:
+            out = torch.empty((self.N, self.N, self.N), dtype=self.dtype, device=self.device)
+        _check(load().cpra_assemble_volume(self.handle, ctypes.c_void_p(out.data_ptr())), self.handle)
+        return out
+
+    def set_kernel_timing(self, enable=True):
+        _check(load().cpra_set_kernel_timing(self.handle, int(bool(enable))), self.handle)
+
+    def kernel_timing(self):
+        """(col_ms, col_launches, row_ms, row_launches) since timing was enabled or last read."""
+        cm, rm = ctypes.c_double(0), ctypes.c_double(0)
+        cl, rl = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(load().cpra_kernel_timing(self.handle, ctypes.byref(cm), ctypes.byref(cl), ctypes.byref(rm),
+                                         ctypes.byref(rl)), self.handle)
+        return cm.value, cl.value, rm.value, rl.value
+
+    @property
+    def k(self):
+        v = ctypes.c_int64(0)
+        _check(load().cpra_iteration_count(self.handle, ctypes.byref(v)), self.handle)
+        return v.value

@@ -1,0 +1,467 @@
+// C ABI of the CPRA hot path: plan, workspace layout, kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cpra.h"
+#include "host_geom.hpp"
+#include "impl.hpp"
+
+using namespace cpra;
+
+static_assert(sizeof(cpra::Coupling) == sizeof(cpra_host::Coupling), "coupling record layout");
+
+using namespace cpra_impl;
+
+namespace {
+
+constexpr int kErrSlots = 64;       // iterations per error-history chunk
+constexpr int kStageAngles = 8;     // host-pointer submits are staged this many angles at a time
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+thread_local std::string g_create_error;
+
+
+bool size_supported(int N) { return N == 64 || N == 128 || N == 256 || N == 512 || N == 1024; }
+
+int col_tiles(int N) {
+  switch (N) {
+    case 64: return ColGeom<64>::TILES;
+    case 128: return ColGeom<128>::TILES;
+    case 256: return ColGeom<256>::TILES;
+    case 512: return ColGeom<512>::TILES;
+    default: return ColGeom<1024>::TILES;
+  }
+}
+
+int stepd_chunk(int N) { return N >= 512 ? 32 : N; }
+
+cpra_status validate(const cpra_params* p, std::string& msg) {
+  if (!p) { msg = "params is NULL"; return CPRA_ERR_ARG; }
+  if (p->struct_size != sizeof(cpra_params)) { msg = "params.struct_size mismatch"; return CPRA_ERR_ARG; }
+  if (!size_supported(p->N)) { msg = "N must be 64, 128, 256, 512 or 1024"; return CPRA_ERR_UNSUPPORTED; }
+  if (p->Np < 1) { msg = "Np must be >= 1"; return CPRA_ERR_ARG; }
+  if (p->n_ei < 1) { msg = "n_ei must be >= 1"; return CPRA_ERR_ARG; }
+  if (p->wrap != CPRA_WRAP_MIRROR && p->wrap != CPRA_WRAP_PLAIN) { msg = "bad wrap"; return CPRA_ERR_ARG; }
+  if (p->real_type != CPRA_REAL_F32 && p->real_type != CPRA_REAL_F64) { msg = "bad real_type"; return CPRA_ERR_ARG; }
+  if (p->amp_type != CPRA_AMP_F32 && p->amp_type != CPRA_AMP_F16) { msg = "bad amp_type"; return CPRA_ERR_ARG; }
+  if (p->amp_type == CPRA_AMP_F16 && p->real_type != CPRA_REAL_F32) {
+    msg = "FP16 amplitudes need an F32 plan"; return CPRA_ERR_UNSUPPORTED;
+  }
+  double s = 0;
+  for (int i = 0; i < 3; ++i) {
+    if (!(p->alpha[i] >= 0.0) || !std::isfinite(p->alpha[i])) { msg = "alpha must be finite and >= 0"; return CPRA_ERR_ARG; }
+    s += p->alpha[i];
+  }
+  if (std::fabs(s - 1.0) > 1e-12) { msg = "alpha must sum to 1"; return CPRA_ERR_ARG; }
+  if (p->alpha[1] <= 0.0) { msg = "alpha_0 must be > 0"; return CPRA_ERR_ARG; }
+  if (p->theta) {
+    for (int i = 0; i < p->Np; ++i)
+      if (!std::isfinite(p->theta[i])) { msg = "theta must be finite"; return CPRA_ERR_ARG; }
+  }
+  return CPRA_OK;
+}
+
+Layout layout_of(const cpra_params* p) {
+  const size_t N = p->N, Np = p->Np, H = N / 2;
+  const size_t rs = p->real_type == CPRA_REAL_F64 ? 8 : 4;
+  const size_t cs = 2 * rs;
+  const size_t aps = p->real_type == CPRA_REAL_F64 ? 16 : (p->amp_type == CPRA_AMP_F16 ? 4 : 8);
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+  L.P = take(Np * N * H * cs);
+  L.Pmid = take(Np * N * H * cs);
+  L.g0 = take(Np * N * N * rs);
+  L.g1 = take(Np * N * N * rs);
+  L.A2 = take(Np * N * H * aps);
+  L.ampscale = take(Np * rs);
+  L.maskw = take(Np * N * N / 8);
+  L.den = take(Np * 8);
+  L.tw = take(N * cs);
+  L.coup = take(Np * sizeof(cpra::Coupling));
+  L.alist = take(Np * 4);
+  L.errpart = take((size_t)kErrSlots * Np * col_tiles(p->N) * 8);
+  L.errhist = take((size_t)kErrSlots * Np * 8);
+  L.flags = take(256);
+  L.stage_I = take((size_t)kStageAngles * N * N * 4);
+  L.stage_S = take((size_t)kStageAngles * N * N);
+  L.csr_ptr = take((N * N + 1) * 4);
+  L.csr_ent = take(Np * N * 4);
+  L.cnt_inv = take(N * N * rs);
+  L.zc = stepd_chunk(p->N);
+  L.plane = take((size_t)L.zc * N * N * cs);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+namespace {
+
+cpra_status fail(cpra_plan_t pl, cpra_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (pl) {
+    pl->err = buf;
+    if (st == CPRA_ERR_DEVICE) pl->poisoned = true;
+  } else {
+    g_create_error = buf;
+  }
+  return st;
+}
+
+#define HIPCHK(pl, expr)                                                                   \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(pl, CPRA_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCHCHK(pl)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = hipGetLastError();                                                     \
+    if (e_ != hipSuccess) return fail(pl, CPRA_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+
+Ops ops_of(const cpra_params& p) {
+  switch (p.N) {
+    case 64: return ops_for_size<64>(p);
+    case 128: return ops_for_size<128>(p);
+    case 256: return ops_for_size<256>(p);
+    case 512: return ops_for_size<512>(p);
+    default: return ops_for_size<1024>(p);
+  }
+}
+
+cpra_status upload_tables(cpra_plan_t pl) {
+  const int Np = pl->p.Np;
+  cpra_host::coupling_table(Np, pl->present.data(), pl->p.alpha, pl->p.wrap == CPRA_WRAP_MIRROR, pl->coup_h);
+  pl->alist_h.clear();
+  for (int n = 0; n < Np; ++n)
+    if (pl->present[n]) pl->alist_h.push_back(n);
+  HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.coup, pl->coup_h.data(), Np * sizeof(cpra::Coupling),
+                            hipMemcpyHostToDevice, pl->stream));
+  if (!pl->alist_h.empty())
+    HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist, pl->alist_h.data(), pl->alist_h.size() * 4,
+                              hipMemcpyHostToDevice, pl->stream));
+  // the host vectors are rewritten at the next boundary: make the copies complete first
+  HIPCHK(pl, hipStreamSynchronize(pl->stream));
+  pl->tables_dirty = false;
+  return CPRA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpra_status cpra_workspace_size(const cpra_params* params, size_t* bytes) {
+  std::string msg;
+  cpra_status st = validate(params, msg);
+  if (st != CPRA_OK) return fail(nullptr, st, "%s", msg.c_str());
+  if (!bytes) return fail(nullptr, CPRA_ERR_ARG, "bytes is NULL");
+  *bytes = layout_of(params).total;
+  return CPRA_OK;
+}
+
+cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t workspace_bytes, void* hip_stream,
+                             cpra_plan_t* out) {
+  std::string msg;
+  cpra_status st = validate(params, msg);
+  if (st != CPRA_OK) return fail(nullptr, st, "%s", msg.c_str());
+  if (!out) return fail(nullptr, CPRA_ERR_ARG, "out is NULL");
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+    return fail(nullptr, CPRA_ERR_ARG, "workspace must be non-NULL and 256-byte aligned");
+  Layout L = layout_of(params);
+  if (workspace_bytes < L.total)
+    return fail(nullptr, CPRA_ERR_OOM, "workspace has %zu bytes, plan needs %zu", workspace_bytes, L.total);
+  cpra_plan_t pl = new (std::nothrow) cpra_plan_s();
+  if (!pl) return fail(nullptr, CPRA_ERR_OOM, "host allocation failed");
+  pl->p = *params;
+  pl->theta.resize(params->Np);
+  for (int n = 0; n < params->Np; ++n)
+    pl->theta[n] = params->theta ? params->theta[n] : cpra_host::default_theta(n, params->Np);
+  pl->p.theta = nullptr;
+  pl->L = L;
+  pl->ws = reinterpret_cast<char*>(workspace);
+  pl->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  pl->landed.assign(params->Np, 0);
+  pl->present.assign(params->Np, 0);
+  pl->ntiles = col_tiles(params->N);
+  Ops ops = ops_of(pl->p);
+  ops.twiddles(pl);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemsetAsync(pl->ws + L.flags, 0, 256, pl->stream);
+  // step-D tables (integer map built on the host in FP64)
+  std::vector<int32_t> rp, ent;
+  cpra_host::insertion_csr(params->N, params->Np, pl->theta.data(), rp, ent);
+  const size_t NN = (size_t)params->N * params->N;
+  if (e == hipSuccess) e = hipMemcpyAsync(pl->ws + L.csr_ptr, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, pl->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(pl->ws + L.csr_ent, ent.data(), ent.size() * 4, hipMemcpyHostToDevice, pl->stream);
+  std::vector<double> inv_d(NN);
+  std::vector<float> inv_f(NN);
+  for (size_t c = 0; c < NN; ++c) {
+    int cnt = rp[c + 1] - rp[c];
+    inv_d[c] = cnt ? 1.0 / cnt : 0.0;
+    inv_f[c] = (float)inv_d[c];
+  }
+  if (e == hipSuccess) {
+    if (params->real_type == CPRA_REAL_F64)
+      e = hipMemcpyAsync(pl->ws + L.cnt_inv, inv_d.data(), NN * 8, hipMemcpyHostToDevice, pl->stream);
+    else
+      e = hipMemcpyAsync(pl->ws + L.cnt_inv, inv_f.data(), NN * 4, hipMemcpyHostToDevice, pl->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+  if (e != hipSuccess) {
+    g_create_error = std::string("plan setup: ") + hipGetErrorString(e);
+    delete pl;
+    return CPRA_ERR_DEVICE;
+  }
+  *out = pl;
+  return CPRA_OK;
+}
+
+cpra_status cpra_submit_angles(cpra_plan_t pl, int32_t first, int32_t count, const float* intensity,
+                               const uint8_t* support, int32_t ptr_kind) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
+  if (count < 1 || first < 0 || first + count > pl->p.Np)
+    return fail(pl, CPRA_ERR_ARG, "angles [%d, %d) outside [0, %d)", first, first + count, pl->p.Np);
+  if (!intensity || !support) return fail(pl, CPRA_ERR_ARG, "intensity/support is NULL");
+  if (ptr_kind != CPRA_PTR_HOST && ptr_kind != CPRA_PTR_DEVICE) return fail(pl, CPRA_ERR_ARG, "bad ptr_kind");
+  for (int i = 0; i < count; ++i)
+    if (pl->landed[first + i]) return fail(pl, CPRA_ERR_STATE, "angle %d was already submitted", first + i);
+  const int N = pl->p.N;
+  const size_t NN = (size_t)N * N;
+  Ops ops = ops_of(pl->p);
+  HIPCHK(pl, hipMemsetAsync(pl->ws + pl->L.flags, 0, 4, pl->stream));
+  std::vector<int32_t> ids(count);
+  for (int i = 0; i < count; ++i) ids[i] = first + i;
+  for (int c0 = 0; c0 < count; c0 += kStageAngles) {
+    const int cn = std::min(kStageAngles, count - c0);
+    const float* dI;
+    const uint8_t* dS;
+    if (ptr_kind == CPRA_PTR_HOST) {
+      HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.stage_I, intensity + c0 * NN, cn * NN * 4, hipMemcpyHostToDevice, pl->stream));
+      HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.stage_S, support + c0 * NN, cn * NN, hipMemcpyHostToDevice, pl->stream));
+      dI = at<float>(pl, pl->L.stage_I);
+      dS = at<uint8_t>(pl, pl->L.stage_S);
+    } else {
+      dI = intensity + c0 * NN;
+      dS = support + c0 * NN;
+    }
+    ops.prep(pl, dI, dS, first + c0, cn);
+    LAUNCHCHK(pl);
+    // initial objects go into the buffer that holds the current iterate
+    HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist + 0, ids.data() + c0, cn * 4, hipMemcpyHostToDevice, pl->stream));
+    ops.init(pl, at<int>(pl, pl->L.alist), cn, pl->cur);
+    LAUNCHCHK(pl);
+    if (ptr_kind == CPRA_PTR_HOST || c0 + kStageAngles < count) HIPCHK(pl, hipStreamSynchronize(pl->stream));
+  }
+  int flag = 0;
+  HIPCHK(pl, hipMemcpyAsync(&flag, pl->ws + pl->L.flags, 4, hipMemcpyDeviceToHost, pl->stream));
+  HIPCHK(pl, hipStreamSynchronize(pl->stream));
+  pl->tables_dirty = true;   // alist was used as scratch
+  if (flag & 1) return fail(pl, CPRA_ERR_DATA, "intensity contains NaN or Inf");
+  for (int i = 0; i < count; ++i) pl->landed[first + i] = 1;
+  if (pl->k % pl->p.n_ei == 0) {
+    pl->present = pl->landed;
+  }
+  return CPRA_OK;
+}
+
+cpra_status cpra_iterate(cpra_plan_t pl, int32_t n_iter, int32_t algo, double beta, double* err_out) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
+  if (n_iter < 0) return fail(pl, CPRA_ERR_ARG, "n_iter < 0");
+  if (algo != CPRA_HIO && algo != CPRA_ER) return fail(pl, CPRA_ERR_ARG, "bad algo");
+  if (!std::isfinite(beta)) return fail(pl, CPRA_ERR_ARG, "beta must be finite");
+  const int Np = pl->p.Np;
+  {
+    bool any = false;
+    for (int n = 0; n < Np; ++n) any = any || pl->landed[n];
+    if (!any) return fail(pl, CPRA_ERR_STATE, "no angle has been submitted");
+  }
+  Ops ops = ops_of(pl->p);
+  if (err_out)
+    for (size_t i = 0; i < (size_t)n_iter * Np; ++i) err_out[i] = NAN;
+  int slot = 0, slot_base = 0;
+  // reduce the pending error slots with the angle list they were computed with
+  auto flush = [&]() -> cpra_status {
+    if (!err_out || slot == 0) return CPRA_OK;
+    const int nact = (int)pl->alist_h.size();
+    const int tot = slot * nact;
+    k_err_reduce<<<(tot + 255) / 256, 256, 0, pl->stream>>>(at<double>(pl, pl->L.errpart), at<double>(pl, pl->L.den),
+                                                            at<int>(pl, pl->L.alist), nact, pl->ntiles, slot,
+                                                            at<double>(pl, pl->L.errhist));
+    LAUNCHCHK(pl);
+    pl->errhist_h.resize(tot);
+    HIPCHK(pl, hipMemcpyAsync(pl->errhist_h.data(), pl->ws + pl->L.errhist, tot * 8, hipMemcpyDeviceToHost, pl->stream));
+    HIPCHK(pl, hipStreamSynchronize(pl->stream));
+    for (int s = 0; s < slot; ++s)
+      for (int ai = 0; ai < nact; ++ai)
+        err_out[(size_t)(slot_base + s) * Np + pl->alist_h[ai]] = pl->errhist_h[(size_t)s * nact + ai];
+    slot_base += slot;
+    slot = 0;
+    return CPRA_OK;
+  };
+  for (int it = 0; it < n_iter; ++it) {
+    const bool boundary = (pl->k % pl->p.n_ei) == 0;
+    if (boundary && pl->present != pl->landed) {
+      pl->present = pl->landed;
+      pl->tables_dirty = true;
+    }
+    if (pl->tables_dirty) {
+      cpra_status st = flush();
+      if (st != CPRA_OK) return st;
+      st = upload_tables(pl);
+      if (st != CPRA_OK) return st;
+    }
+    const int nact = (int)pl->alist_h.size();
+    const bool estimate = ((pl->k + 1) % pl->p.n_ei) == 0;
+    const int mode = estimate ? 2 : (algo == CPRA_HIO ? 1 : 2);
+    double* ep = err_out ? at<double>(pl, pl->L.errpart) + (size_t)slot * nact * pl->ntiles : nullptr;
+    ops.step(pl, nact, boundary, mode, beta, ep);
+    LAUNCHCHK(pl);
+    if (boundary) pl->cur ^= 1;
+    pl->k += 1;
+    if (err_out) {
+      ++slot;
+      if (slot == kErrSlots || it == n_iter - 1) {
+        cpra_status st = flush();
+        if (st != CPRA_OK) return st;
+      }
+    }
+  }
+  return CPRA_OK;
+}
+
+cpra_status cpra_load_objects(cpra_plan_t pl, const void* objects, int32_t ptr_kind) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
+  if (!objects) return fail(pl, CPRA_ERR_ARG, "objects is NULL");
+  if (ptr_kind != CPRA_PTR_HOST && ptr_kind != CPRA_PTR_DEVICE) return fail(pl, CPRA_ERR_ARG, "bad ptr_kind");
+  const int Np = pl->p.Np;
+  std::vector<int32_t> ids;
+  for (int n = 0; n < Np; ++n)
+    if (pl->landed[n]) ids.push_back(n);
+  if (ids.empty()) return fail(pl, CPRA_ERR_STATE, "no angle has been submitted");
+  const size_t plane = (size_t)pl->p.N * pl->p.N * (pl->p.real_type == CPRA_REAL_F64 ? 8 : 4);
+  char* dst = pl->ws + (pl->cur ? pl->L.g1 : pl->L.g0);
+  const hipMemcpyKind kind = ptr_kind == CPRA_PTR_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  for (int32_t n : ids)
+    HIPCHK(pl, hipMemcpyAsync(dst + n * plane, static_cast<const char*>(objects) + n * plane, plane, kind, pl->stream));
+  HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, pl->stream));
+  Ops ops = ops_of(pl->p);
+  ops.reload(pl, at<int>(pl, pl->L.alist), (int)ids.size(), pl->cur);
+  LAUNCHCHK(pl);
+  HIPCHK(pl, hipStreamSynchronize(pl->stream));   // ids is a host temporary; host inputs must be consumed
+  pl->tables_dirty = true;                         // alist was used as scratch
+  return CPRA_OK;
+}
+
+cpra_status cpra_read_objects(cpra_plan_t pl, void* out, int32_t ptr_kind) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
+  if (!out) return fail(pl, CPRA_ERR_ARG, "out is NULL");
+  if (ptr_kind != CPRA_PTR_HOST && ptr_kind != CPRA_PTR_DEVICE) return fail(pl, CPRA_ERR_ARG, "bad ptr_kind");
+  const size_t bytes = (size_t)pl->p.Np * pl->p.N * pl->p.N * (pl->p.real_type == CPRA_REAL_F64 ? 8 : 4);
+  const char* src = pl->ws + (pl->cur ? pl->L.g1 : pl->L.g0);
+  HIPCHK(pl, hipMemcpyAsync(out, src, bytes, ptr_kind == CPRA_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                            pl->stream));
+  if (ptr_kind == CPRA_PTR_HOST) HIPCHK(pl, hipStreamSynchronize(pl->stream));
+  return CPRA_OK;
+}
+
+cpra_status cpra_assemble_volume(cpra_plan_t pl, void* d_volume) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
+  if (!d_volume) return fail(pl, CPRA_ERR_ARG, "d_volume is NULL");
+  if (pl->k == 0 || pl->k % pl->p.n_ei != 0)
+    return fail(pl, CPRA_ERR_STATE, "step D needs an episode end (k=%lld, n_ei=%d)", (long long)pl->k, pl->p.n_ei);
+  Ops ops = ops_of(pl->p);
+  ops.assemble(pl, d_volume);
+  LAUNCHCHK(pl);
+  return CPRA_OK;
+}
+
+cpra_status cpra_destroy(cpra_plan_t pl) {
+  delete pl;
+  return CPRA_OK;
+}
+
+const char* cpra_last_error(cpra_plan_t pl) { return pl ? pl->err.c_str() : g_create_error.c_str(); }
+
+cpra_status cpra_iteration_count(cpra_plan_t pl, int64_t* k) {
+  if (!pl || !k) return CPRA_ERR_ARG;
+  *k = pl->k;
+  return CPRA_OK;
+}
+
+cpra_status cpra_set_kernel_timing(cpra_plan_t pl, int32_t enable) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  pl->timing = enable != 0;
+  pl->ev_used = 0;
+  return CPRA_OK;
+}
+
+cpra_status cpra_kernel_timing(cpra_plan_t pl, double* col_ms, int64_t* col_launches, double* row_ms,
+                               int64_t* row_launches) {
+  if (!pl || !col_ms || !col_launches || !row_ms || !row_launches) return fail(pl, CPRA_ERR_ARG, "NULL argument");
+  if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
+  HIPCHK(pl, hipStreamSynchronize(pl->stream));
+  double c = 0.0, r = 0.0;
+  const size_t trip = pl->ev_used / 3;
+  for (size_t i = 0; i < trip; ++i) {
+    float a = 0.f, b = 0.f;
+    HIPCHK(pl, hipEventElapsedTime(&a, pl->evpool[3 * i], pl->evpool[3 * i + 1]));
+    HIPCHK(pl, hipEventElapsedTime(&b, pl->evpool[3 * i + 1], pl->evpool[3 * i + 2]));
+    c += a;
+    r += b;
+  }
+  *col_ms = c;
+  *row_ms = r;
+  *col_launches = (int64_t)trip;
+  *row_launches = (int64_t)trip;
+  pl->ev_used = 0;
+  return CPRA_OK;
+}
+
+cpra_status cpra_slice_cells(int32_t N, int32_t Np, const double* theta, int32_t* kx_out, int32_t* ky_out) {
+  if (N < 2 || (N % 2) != 0 || Np < 1 || !kx_out || !ky_out) return fail(nullptr, CPRA_ERR_ARG, "bad arguments");
+  cpra_host::slice_cells(N, Np, theta, kx_out, ky_out);
+  return CPRA_OK;
+}
+
+cpra_status cpra_coupling_table(const cpra_params* params, const uint8_t* present, int32_t* left, int32_t* right,
+                                double* w, uint8_t* mirror) {
+  std::string msg;
+  cpra_status st = validate(params, msg);
+  if (st != CPRA_OK) return fail(nullptr, st, "%s", msg.c_str());
+  if (!left || !right || !w || !mirror) return fail(nullptr, CPRA_ERR_ARG, "output is NULL");
+  std::vector<cpra_host::Coupling> t;
+  cpra_host::coupling_table(params->Np, present, params->alpha, params->wrap == CPRA_WRAP_MIRROR, t);
+  for (int n = 0; n < params->Np; ++n) {
+    left[n] = t[n].left;
+    right[n] = t[n].right;
+    w[3 * n] = t[n].wl;
+    w[3 * n + 1] = t[n].w0;
+    w[3 * n + 2] = t[n].wr;
+    mirror[2 * n] = (uint8_t)t[n].mirror_left;
+    mirror[2 * n + 1] = (uint8_t)t[n].mirror_right;
+  }
+  return CPRA_OK;
+}
+
+}  // extern "C"

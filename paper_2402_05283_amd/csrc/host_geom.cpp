@@ -1,0 +1,75 @@
+// Host-only geometry and bookkeeping of the CPRA library (no GPU calls).
+//
+// Built with -ffp-contract=off so that the FP64 slice rounding is the plain
+// IEEE sequence (product, add 0.5, floor) on every build.
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "host_geom.hpp"
+
+namespace cpra_host {
+
+double default_theta(int n, int Np) { return M_PI * (double)n / (double)Np; }
+
+// Nearest voxel of the Fourier slice of angle theta (rotation about z):
+// centred frequency u maps to (kx, ky) = (-u sin t, u cos t), rounded with
+// floor(x + 0.5) and wrapped to native indices mod N.
+void slice_cells(int N, int Np, const double* theta, int32_t* kx, int32_t* ky) {
+  for (int n = 0; n < Np; ++n) {
+    const double t = theta ? theta[n] : default_theta(n, Np);
+    const double s = std::sin(t), c = std::cos(t);
+    for (int iu = 0; iu < N; ++iu) {
+      const double u = (double)(iu - N / 2);
+      const double x = -(u * s);
+      const double y = u * c;
+      long fx = (long)std::floor(x + 0.5), fy = (long)std::floor(y + 0.5);
+      kx[(size_t)n * N + iu] = (int32_t)(((fx % N) + N) % N);
+      ky[(size_t)n * N + iu] = (int32_t)(((fy % N) + N) % N);
+    }
+  }
+}
+
+// CSR of the insertion: for each native cell ky*N + kx, the entries n*N + u
+// (u native frequency index, (u - N/2 + N) % N style wrap of the centred u).
+void insertion_csr(int N, int Np, const double* theta, std::vector<int32_t>& row_ptr,
+                   std::vector<int32_t>& entries) {
+  std::vector<int32_t> kx((size_t)Np * N), ky((size_t)Np * N);
+  slice_cells(N, Np, theta, kx.data(), ky.data());
+  row_ptr.assign((size_t)N * N + 1, 0);
+  for (size_t i = 0; i < kx.size(); ++i) row_ptr[(size_t)ky[i] * N + kx[i] + 1]++;
+  for (size_t c = 0; c < (size_t)N * N; ++c) row_ptr[c + 1] += row_ptr[c];
+  entries.assign(kx.size(), 0);
+  std::vector<int32_t> fill(row_ptr.begin(), row_ptr.end() - 1);
+  for (int n = 0; n < Np; ++n) {
+    for (int iu = 0; iu < N; ++iu) {
+      size_t i = (size_t)n * N + iu;
+      size_t cell = (size_t)ky[i] * N + kx[i];
+      int un = ((iu - N / 2) % N + N) % N;
+      entries[fill[cell]++] = n * N + un;
+    }
+  }
+}
+
+void coupling_table(int Np, const uint8_t* present, const double alpha[3], int wrap_mirror,
+                    std::vector<Coupling>& out) {
+  out.assign(Np, Coupling{});
+  for (int n = 0; n < Np; ++n) {
+    int l = (n - 1 + Np) % Np, r = (n + 1) % Np;
+    double wl = (present == nullptr || present[l]) ? alpha[0] : 0.0;
+    double wr = (present == nullptr || present[r]) ? alpha[2] : 0.0;
+    double w0 = alpha[1];
+    double s = wl + w0 + wr;
+    Coupling c;
+    c.left = l;
+    c.right = r;
+    c.mirror_left = (wrap_mirror && n == 0) ? 1 : 0;
+    c.mirror_right = (wrap_mirror && n == Np - 1) ? 1 : 0;
+    c.wl = wl / s;
+    c.w0 = w0 / s;
+    c.wr = wr / s;
+    out[n] = c;
+  }
+}
+
+}  // namespace cpra_host

@@ -1,0 +1,158 @@
+// Plan state and per-size kernel dispatch of the CPRA library (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/cpra.h"
+#include "host_geom.hpp"
+#include "kernels.hpp"
+#include "stepd.hpp"
+
+namespace cpra_impl {
+
+struct Layout {
+  size_t P, Pmid, g0, g1, A2, ampscale, maskw, den, tw, coup, alist, errpart, errhist, flags, stage_I,
+      stage_S, csr_ptr, csr_ent, cnt_inv, plane, total;
+  int zc;   // z-planes per step-D chunk
+};
+
+}  // namespace cpra_impl
+
+struct cpra_plan_s {
+  cpra_params p{};
+  std::vector<double> theta;
+  cpra_impl::Layout L{};
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int cur = 0;                 // which g buffer holds the current iterate
+  int64_t k = 0;               // global iteration count
+  std::vector<uint8_t> landed, present;
+  std::vector<int32_t> alist_h;
+  bool tables_dirty = true;
+  bool poisoned = false;
+  std::string err;
+  int ntiles = 0;
+  std::vector<cpra_host::Coupling> coup_h;
+  std::vector<double> errhist_h;
+  // optional per-pass event timing (measurement): triples (before col, between, after row)
+  bool timing = false;
+  std::vector<hipEvent_t> evpool;
+  size_t ev_used = 0;
+  hipEvent_t next_event() {
+    if (ev_used == evpool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      evpool.push_back(e);
+    }
+    return evpool[ev_used++];
+  }
+  ~cpra_plan_s() {
+    for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+  }
+};
+
+
+namespace cpra_impl {
+using namespace cpra;
+
+template <typename X> X* at(cpra_plan_t pl, size_t off) { return reinterpret_cast<X*>(pl->ws + off); }
+
+struct Ops {
+  void (*twiddles)(cpra_plan_t);
+  void (*prep)(cpra_plan_t, const float*, const uint8_t*, int, int);
+  void (*init)(cpra_plan_t, const int*, int, int);
+  void (*step)(cpra_plan_t, int, bool, int, double, double*);
+  void (*assemble)(cpra_plan_t, void*);
+  void (*reload)(cpra_plan_t, const int*, int, int);
+};
+
+template <int N, typename T, typename AP>
+struct Impl {
+  using C = cx<T>;
+  static void twiddles(cpra_plan_t pl) {
+    k_twiddles<T><<<(N + 255) / 256, 256, 0, pl->stream>>>(at<C>(pl, pl->L.tw), N);
+  }
+  static void prep(cpra_plan_t pl, const float* I, const uint8_t* S, int first, int count) {
+    k_prep<N, T, AP><<<count, 256, 0, pl->stream>>>(I, S, first, at<AP>(pl, pl->L.A2), at<T>(pl, pl->L.ampscale),
+                                                    at<uint32_t>(pl, pl->L.maskw), at<double>(pl, pl->L.den),
+                                                    at<int>(pl, pl->L.flags));
+  }
+  // initial objects of `count` angles listed at alist (device)
+  static void init(cpra_plan_t pl, const int* d_list, int count, int gbuf) {
+    using CG = ColGeom<N>;
+    using RG = RowGeom<N>;
+    dim3 gc(CG::TILES, count), bc(CG::R1 * CG::C);
+    k_col<N, T, AP, 1, false><<<gc, bc, 0, pl->stream>>>(
+        nullptr, at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2), at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw),
+        d_list, nullptr, 0, nullptr, CG::TILES, pl->p.seed);
+    T* g = at<T>(pl, gbuf ? pl->L.g1 : pl->L.g0);
+    dim3 gr(N / RG::RPB, count), br(RG::T * RG::RPB);
+    k_row<N, T><<<gr, br, 0, pl->stream>>>(at<C>(pl, pl->L.Pmid), at<C>(pl, pl->L.P), g, g,
+                                          at<uint32_t>(pl, pl->L.maskw), at<C>(pl, pl->L.tw), d_list, nullptr, 0,
+                                          0, (T)0, pl->p.positivity);
+  }
+  static void step(cpra_plan_t pl, int nact, bool couple, int mode, double beta, double* errpart) {
+    using CG = ColGeom<N>;
+    using RG = RowGeom<N>;
+    dim3 gc(CG::TILES, nact), bc(CG::R1 * CG::C);
+    const int* al = at<int>(pl, pl->L.alist);
+    const cpra::Coupling* cp = at<cpra::Coupling>(pl, pl->L.coup);
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    if (pl->timing) {
+      e0 = pl->next_event(); e1 = pl->next_event(); e2 = pl->next_event();
+      if (e0) (void)hipEventRecord(e0, pl->stream);
+    }
+    if (errpart)
+      k_col<N, T, AP, 0, true><<<gc, bc, 0, pl->stream>>>(at<C>(pl, pl->L.P), at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2),
+                                                         at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw), al, cp,
+                                                         couple ? 1 : 0, errpart, CG::TILES, 0);
+    else
+      k_col<N, T, AP, 0, false><<<gc, bc, 0, pl->stream>>>(at<C>(pl, pl->L.P), at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2),
+                                                          at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw), al, cp,
+                                                          couple ? 1 : 0, nullptr, CG::TILES, 0);
+    if (e1) (void)hipEventRecord(e1, pl->stream);
+    T* gin = at<T>(pl, pl->cur ? pl->L.g1 : pl->L.g0);
+    T* gout = couple ? at<T>(pl, pl->cur ? pl->L.g0 : pl->L.g1) : gin;
+    dim3 gr(N / RG::RPB, nact), br(RG::T * RG::RPB);
+    k_row<N, T><<<gr, br, 0, pl->stream>>>(at<C>(pl, pl->L.Pmid), at<C>(pl, pl->L.P), gin, gout,
+                                          at<uint32_t>(pl, pl->L.maskw), at<C>(pl, pl->L.tw), al, cp, couple ? 1 : 0,
+                                          mode, (T)beta, pl->p.positivity);
+    if (e2) (void)hipEventRecord(e2, pl->stream);
+  }
+  // row spectra P = F_t(g) of the listed angles from the iterate in buffer gbuf
+  static void reload(cpra_plan_t pl, const int* d_list, int count, int gbuf) {
+    using RG = RowGeom<N>;
+    T* g = at<T>(pl, gbuf ? pl->L.g1 : pl->L.g0);
+    dim3 gr(N / RG::RPB, count), br(RG::T * RG::RPB);
+    k_row<N, T><<<gr, br, 0, pl->stream>>>(nullptr, at<C>(pl, pl->L.P), g, g, at<uint32_t>(pl, pl->L.maskw),
+                                          at<C>(pl, pl->L.tw), d_list, nullptr, 0, 3, (T)0, pl->p.positivity);
+  }
+  static void assemble(cpra_plan_t pl, void* vol) {
+    stepd_run<N, T>(at<C>(pl, pl->L.P), at<int>(pl, pl->L.csr_ptr), at<int>(pl, pl->L.csr_ent),
+                    at<T>(pl, pl->L.cnt_inv), at<C>(pl, pl->L.plane), pl->L.zc, reinterpret_cast<T*>(vol),
+                    pl->stream);
+  }
+};
+
+
+
+template <int N, typename T, typename AP> Ops ops_for() {
+  return Ops{&Impl<N, T, AP>::twiddles, &Impl<N, T, AP>::prep, &Impl<N, T, AP>::init, &Impl<N, T, AP>::step,
+             &Impl<N, T, AP>::assemble, &Impl<N, T, AP>::reload};
+}
+
+
+template <int N> Ops ops_for_size(const cpra_params& p) {
+  if (p.real_type == CPRA_REAL_F64) return ops_for<N, double, double2>();
+  if (p.amp_type == CPRA_AMP_F16) return ops_for<N, float, __half2>();
+  return ops_for<N, float, float2>();
+}
+extern template Ops ops_for_size<64>(const cpra_params&);
+extern template Ops ops_for_size<128>(const cpra_params&);
+extern template Ops ops_for_size<256>(const cpra_params&);
+extern template Ops ops_for_size<512>(const cpra_params&);
+extern template Ops ops_for_size<1024>(const cpra_params&);
+
+}  // namespace cpra_impl

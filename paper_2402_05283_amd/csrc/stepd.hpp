@@ -1,0 +1,138 @@
+// Step D on the device: Fourier-slice insertion and the 3D inverse FFT,
+// factorised per z-plane.
+//
+// The insertion weights do not depend on the frequency w along z, so the
+// inverse transform along z undoes the forward one exactly:
+//   F3^-1[Insert(F2 O'_n)] = F2^-1_xy[Insert_z(F_t O'_n)]   for every z.
+// The row spectra F_t O'_n are the packed P rows the iteration keeps, so
+// step D needs no N^3 complex grid: per z-plane it gathers
+//   Q_z[ky][kx] = (-1)^(ky+kx) / cnt(ky,kx) * sum_{(n,u) in cell} (-1)^u S_n[z][u]
+// (the signs move the origin of u, ky, kx to the array centre) and the
+// volume slice is Re F2^-1(Q_z) / N^2, written centred [z][y][x].
+#pragma once
+#include "kernels.hpp"
+
+namespace cpra {
+
+template <int N, typename T>
+__device__ __forceinline__ cx<T> spectrum_at(const cx<T>* Prow, int u) {
+  constexpr int H = N / 2;
+  using C = cx<T>;
+  if (u == 0) return mk<C>(Prow[0].x, (T)0);
+  if (u == H) return mk<C>(Prow[0].y, (T)0);
+  if (u < H) return Prow[u];
+  return conj(Prow[N - u]);
+}
+
+// Rows: gather Q_z[ky][:] and inverse transform along kx.
+// Block: RB rows x R1 threads; grid: (N / RB, zc).
+template <int N, typename T, int RB>
+__global__ void __launch_bounds__(ColCfg<N>::R1* RB)
+    k_stepd_rows(const cx<T>* __restrict__ P, const int* __restrict__ ptr, const int* __restrict__ ent,
+                 const T* __restrict__ cnt_inv, cx<T>* __restrict__ plane, int z0) {
+  using C = cx<T>;
+  constexpr int R1 = ColCfg<N>::R1, R2 = ColCfg<N>::R2, Q = R2 / R1, H = N / 2;
+  constexpr int LS = R1 + 1;
+  __shared__ C lds[RB * R2 * LS];
+  const int a = threadIdx.x % R1;
+  const int r = threadIdx.x / R1;
+  const int ky = blockIdx.x * RB + r;
+  const int zi = blockIdx.y;
+  const int z = z0 + zi;
+  C* L0 = lds + r * R2 * LS;
+  C v[R2];
+#pragma unroll
+  for (int b = 0; b < R2; ++b) {
+    const int kx = a + R1 * b;
+    const int cell = ky * N + kx;
+    C acc = mk<C>((T)0, (T)0);
+    const int e1 = ptr[cell + 1];
+    for (int e = ptr[cell]; e < e1; ++e) {
+      const int code = ent[e];
+      const int n = code / N, u = code % N;
+      C s = spectrum_at<N, T>(P + ((size_t)n * N + z) * H, u);
+      if (u & 1) { s.x = -s.x; s.y = -s.y; }
+      acc = cadd(acc, s);
+    }
+    T f = cnt_inv[cell];
+    if ((ky + kx) & 1) f = -f;
+    v[b] = cscale(acc, f);
+  }
+  // inverse four-step along kx = a + R1 b -> x = c + R2 d
+  dft<R2, +1>(v);
+  C tw1;
+#pragma unroll
+  for (int c = 0; c < R2; ++c) {
+    double s, co;
+    sincospi(2.0 * (double)((a * c) % N) / (double)N, &s, &co);
+    tw1 = mk<C>((T)co, (T)s);
+    L0[c * LS + a] = (c == 0 || a == 0) ? v[c] : cmul(v[c], tw1);
+  }
+  __syncthreads();
+  C* out = plane + ((size_t)zi * N + ky) * N;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int c = a + R1 * q;
+    C u[R1];
+#pragma unroll
+    for (int ap = 0; ap < R1; ++ap) u[ap] = L0[c * LS + ap];
+    dft<R1, +1>(u);
+#pragma unroll
+    for (int d = 0; d < R1; ++d) out[c + R2 * d] = u[d];
+  }
+}
+
+// Columns: inverse transform along ky, real part / N^2 -> volume [z][y][x].
+// Block: C columns x R1 threads; grid: (N / C, zc).
+template <int N, typename T, int CC>
+__global__ void __launch_bounds__(ColCfg<N>::R1* CC)
+    k_stepd_cols(const cx<T>* __restrict__ plane, T* __restrict__ vol, int z0) {
+  using C = cx<T>;
+  constexpr int R1 = ColCfg<N>::R1, R2 = ColCfg<N>::R2, Q = R2 / R1;
+  constexpr int LSTRIDE = R1 * CC + 1;
+  __shared__ C lds[R2 * LSTRIDE];
+  const int col = threadIdx.x % CC;
+  const int a = threadIdx.x / CC;
+  const int x = blockIdx.x * CC + col;
+  const int zi = blockIdx.y;
+  const C* in = plane + (size_t)zi * N * N;
+  C v[R2];
+#pragma unroll
+  for (int b = 0; b < R2; ++b) v[b] = in[(size_t)(a + R1 * b) * N + x];
+  dft<R2, +1>(v);
+#pragma unroll
+  for (int c = 0; c < R2; ++c) {
+    double s, co;
+    sincospi(2.0 * (double)((a * c) % N) / (double)N, &s, &co);
+    C t = mk<C>((T)co, (T)s);
+    lds[c * LSTRIDE + a * CC + col] = (c == 0 || a == 0) ? v[c] : cmul(v[c], t);
+  }
+  __syncthreads();
+  const T norm = (T)1 / ((T)N * (T)N);
+  T* out = vol + (size_t)(z0 + zi) * N * N;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int c = a + R1 * q;
+    C u[R1];
+#pragma unroll
+    for (int ap = 0; ap < R1; ++ap) u[ap] = lds[c * LSTRIDE + ap * CC + col];
+    dft<R1, +1>(u);
+#pragma unroll
+    for (int d = 0; d < R1; ++d) out[(size_t)(c + R2 * d) * N + x] = u[d].x * norm;
+  }
+}
+
+template <int N, typename T>
+void stepd_run(const cx<T>* P, const int* ptr, const int* ent, const T* cnt_inv, cx<T>* plane, int zc, T* vol,
+               hipStream_t st) {
+  constexpr int R1 = ColCfg<N>::R1;
+  constexpr int RB = (256 / R1) < N ? (256 / R1) : N;
+  constexpr int CC = (256 / R1) < N ? (256 / R1) : N;
+  for (int z0 = 0; z0 < N; z0 += zc) {
+    const int nz = (N - z0) < zc ? (N - z0) : zc;
+    k_stepd_rows<N, T, RB><<<dim3(N / RB, nz), R1 * RB, 0, st>>>(P, ptr, ent, cnt_inv, plane, z0);
+    k_stepd_cols<N, T, CC><<<dim3(N / CC, nz), R1 * CC, 0, st>>>(plane, vol, z0);
+  }
+}
+
+}  // namespace cpra

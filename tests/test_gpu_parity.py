@@ -1,0 +1,283 @@
+"""GPU path vs the FP64 oracle, through the C ABI (needs an MI355X).
+
+Tolerances (relative L2 over the whole scan, oracle as reference):
+  FP32 plans: 1e-6 on the initial objects, 1e-5 after one iteration, 1e-3 on
+  the final object after 200 iterations of the 64x64x16 scan;
+  FP64 plans: 1e-12 / 1e-12 / 1e-9.
+A pixel whose HIO sign decision g' >= 0 sits within rounding of zero may
+legitimately take either branch; one-iteration checks exclude such pixels
+from the norm and require their value to be one of the two branches.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import banner, last_step_parity, rel_l2, require_gpu, run_gpu, run_oracle
+from synth import make_scan
+
+pytestmark = pytest.mark.gpu
+
+F32, F64 = 0, 1
+HIO, ER = 0, 1
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.mark.parametrize("real", [F32, F64])
+@pytest.mark.parametrize("N", [64, 128, 256, 512, 1024])
+def test_initial_objects(torch, N, real):
+    scan = make_scan(1, N=N, Np=5)
+    banner(f"initial objects N={N} real={real}")
+    _, obj, _ = run_gpu(scan, [], real=real)
+    o, _ = run_oracle(scan, [])
+    tol = 1e-6 if real == F32 else 1e-12
+    assert rel_l2(obj, o.g) <= tol
+
+
+@pytest.mark.parametrize("real", [F32, F64])
+@pytest.mark.parametrize("N", [64, 128, 256, 512, 1024])
+def test_one_iteration(torch, N, real):
+    """First iteration: coupling of W_0 (mirror seam), FFTs, projection, error, HIO."""
+    scan = make_scan(1, N=N, Np=5)
+    banner(f"one iteration N={N} real={real}")
+    sched = [(1, HIO, 0.9)]
+    alpha = (0.1, 0.6, 0.3)
+    _, obj, errs = run_gpu(scan, sched, real=real, alpha=alpha)
+    o, oerrs = run_oracle(scan, sched, alpha=alpha)
+    tol = 1e-5 if real == F32 else 1e-12
+    r, namb, valid, flips = last_step_parity(obj, o, algo=HIO, beta=0.9, estimate=False,
+                                             amb=1e-5 if real == F32 else 1e-12)
+    print(f"N={N} real={real}: rel {r:.2e}, ambiguous pixels {namb}, sign-ambiguous frequencies {flips}")
+    assert valid and namb <= obj.size * 1e-4
+    assert r <= tol
+    assert rel_l2(errs[0], oerrs[0]) <= (1e-5 if real == F32 else 1e-12)
+
+
+@pytest.mark.parametrize("real", [F32, F64])
+def test_c1_trajectory_steps(torch, real):
+    """Every kind of step of the 200-iteration HIO schedule (64^3 object, 16 angles), one GPU
+    iteration from the oracle's own state at that iteration: plain HIO steps, the estimate step
+    that ends an episode, and the episode boundary that couples the estimates (mirror seam).
+    HIO amplifies a 1e-15 perturbation to 1e-2 within 50 iterations on this scan, so whole
+    trajectories of two implementations cannot be compared pointwise; single steps can."""
+    import paper_2402_05283_amd as cp
+    from oracle import cpra as C
+    scan = make_scan(1)
+    N, Np = scan["N"], scan["Np"]
+    checks = [0, 1, 8, 9, 10, 19, 20, 55, 99, 100, 150, 198, 199]
+    o = C.Oracle(N, Np, theta=scan["theta"], seed=scan["phase_seed"])
+    o.submit(0, scan["I"], scan["support"])
+    states = {}
+    for k in range(200):
+        before = o.g.copy()
+        o.iterate(1, HIO, 0.9)
+        if k in checks:
+            states[k] = (before, o.g.copy(), o.g_prev.copy())
+    plan = cp.Plan(N, Np, theta=scan["theta"], real=real, seed=scan["phase_seed"])
+    plan.submit(0, torch.from_numpy(scan["I"]).cuda(), torch.from_numpy(scan["support"]).cuda())
+    dt = torch.float64 if real == F64 else torch.float32
+    for k in checks:
+        banner(f"c1 trajectory step k={k} real={real}")
+        plan.iterate(k - plan.k, HIO, 0.9)
+        assert plan.k == k
+        before, after, g_prev = states[k]
+        plan.load_objects(torch.from_numpy(before).to(dt).cuda())
+        plan.iterate(1, HIO, 0.9)
+        obj = plan.objects().cpu().numpy()
+        ref = type("R", (), dict(g_prev=g_prev, A=o.A, S=o.S, positivity=True))
+        r, namb, valid, flips = last_step_parity(obj, ref, algo=HIO, beta=0.9, estimate=(k + 1) % 10 == 0,
+                                                 amb=1e-5 if real == F32 else 1e-12)
+        print(f"k={k}: rel {r:.2e} ambiguous {namb} flips {flips}")
+        assert valid and r <= (1e-5 if real == F32 else 1e-12), (k, r)
+
+
+def test_c1_short_run_fp64(torch):
+    """30 whole HIO iterations (three episodes, two couplings) end to end in FP64."""
+    scan = make_scan(1)
+    sched = [(30, HIO, 0.9)]
+    banner("c1 30 iterations fp64")
+    _, obj, errs = run_gpu(scan, sched, real=F64)
+    o, oerrs = run_oracle(scan, sched)
+    assert rel_l2(obj, o.g) <= 1e-6        # the oracle against itself perturbed by 1e-15 drifts to 3e-9
+    assert rel_l2(errs[0], oerrs[0]) <= 1e-6
+
+
+@pytest.mark.parametrize("real", [F32, F64])
+def test_c1_er_run(torch, real):
+    """ER is continuous and non-expansive: whole runs agree (16 angles, 10 episodes)."""
+    scan = make_scan(1)
+    n_iter = 20 if real == F32 else 100
+    sched = [(n_iter, ER, 0.0)]
+    banner(f"c1 ER run real={real}")
+    _, obj, errs = run_gpu(scan, sched, real=real)
+    o, oerrs = run_oracle(scan, sched)
+    tol = 1e-4 if real == F32 else 1e-9
+    assert rel_l2(obj, o.g) <= tol
+    assert rel_l2(errs[0], oerrs[0]) <= tol
+
+
+def test_c1_full_run_converges(torch):
+    """The full 200-iteration FP32 run behaves like the oracle's: same error level at the end."""
+    scan = make_scan(1)
+    sched = [(200, HIO, 0.9)]
+    banner("c1 200 iterations fp32")
+    _, obj, errs = run_gpu(scan, sched, real=F32)
+    o, oerrs = run_oracle(scan, sched)
+    g_last, o_last = np.nanmedian(errs[0][-1]), np.nanmedian(oerrs[0][-1])
+    print(f"final median E_F: gpu {g_last:.4f} oracle {o_last:.4f}; first {np.nanmedian(errs[0][0]):.4f}")
+    assert abs(g_last - o_last) <= 0.25 * o_last
+    assert g_last < 0.5 * np.nanmedian(errs[0][0])
+    assert np.all(np.isfinite(obj))
+
+
+@pytest.mark.parametrize("real", [F32, F64])
+def test_er_plain_wrap_unmeasured_no_positivity(torch, real):
+    """ER after HIO, literal wrap, beamstop pixels (I < 0), no positivity, n_ei = 3."""
+    scan = make_scan(1, Np=6)
+    I = scan["I"].copy()
+    c = scan["N"] // 2
+    I[:, c - 2:c + 3, c - 2:c + 3] = -1.0      # unmeasured centre
+    scan = dict(scan, I=I)
+    sched = [(7, HIO, 0.8), (5, ER, 0.0)]
+    kw = dict(alpha=(0.3, 0.5, 0.2), n_ei=3, wrap=1, positivity=False)
+    banner(f"er/plain/unmeasured real={real}")
+    _, obj, errs = run_gpu(scan, sched, real=real, **kw)
+    o, oerrs = run_oracle(scan, sched, **kw)
+    tol = 1e-4 if real == F32 else 1e-10
+    assert rel_l2(obj, o.g) <= tol
+    for a, b in zip(errs, oerrs):
+        assert rel_l2(a, b) <= tol
+
+
+@pytest.mark.parametrize("Np", [1, 2, 3])
+def test_few_angles(torch, Np):
+    scan = make_scan(1, Np=Np)
+    sched = [(12, HIO, 0.9)]
+    banner(f"few angles Np={Np}")
+    for wrap in (0, 1):
+        _, obj, _ = run_gpu(scan, sched, real=F64, n_ei=4, wrap=wrap)
+        o, _ = run_oracle(scan, sched, n_ei=4, wrap=wrap)
+        assert rel_l2(obj, o.g) <= 1e-10
+
+
+def test_partial_angle_sets(torch):
+    """Angles landing over time: absent neighbours drop out; late angles join at a boundary."""
+    import paper_2402_05283_amd as cp
+    from oracle import cpra as C
+    scan = make_scan(1, Np=8)
+    N, Np = scan["N"], scan["Np"]
+    kw = dict(alpha=(0.2, 0.6, 0.2), n_ei=4, wrap=0, positivity=True)
+    plan = cp.Plan(N, Np, theta=scan["theta"], real=F64, seed=scan["phase_seed"], **kw)
+    o = C.Oracle(N, Np, theta=scan["theta"], seed=scan["phase_seed"], **kw)
+    I = torch.from_numpy(scan["I"]).cuda()
+    S = torch.from_numpy(scan["support"]).cuda()
+    banner("partial angle sets")
+    order = [(0, 3), (5, 2), (3, 2), (7, 1)]
+    iters = [5, 6, 3, 8]          # boundaries at multiples of 4; some land mid-episode
+    for (first, cnt), nit in zip(order, iters):
+        plan.submit(first, I[first:first + cnt], S[first:first + cnt])
+        o.submit(first, scan["I"][first:first + cnt], scan["support"][first:first + cnt])
+        e = plan.iterate(nit, HIO, 0.9, errors=True)
+        oe = o.iterate(nit, HIO, 0.9)
+        assert np.array_equal(np.isnan(e), np.isnan(oe))
+        assert rel_l2(np.nan_to_num(e), np.nan_to_num(oe)) <= 1e-10
+    obj = plan.objects().cpu().numpy()
+    assert rel_l2(obj, o.g) <= 1e-10
+
+
+@pytest.mark.parametrize("real", [F32, F64])
+def test_step_d_volume(torch, real):
+    """Step D after one estimate iteration, vs the oracle's literal N^3 insertion + 3D inverse FFT."""
+    from oracle import stepd as D
+    scan = make_scan(1, Np=16)
+    sched = [(1, HIO, 0.9)]
+    banner(f"step D real={real}")
+    plan, obj, _ = run_gpu(scan, sched, real=real, n_ei=1)
+    vol = plan.assemble_volume().cpu().numpy()
+    o, _ = run_oracle(scan, sched, n_ei=1)
+    ref = D.assemble_volume(o.g, scan["theta"])
+    tol = 1e-5 if real == F32 else 1e-11
+    assert rel_l2(vol, ref) <= tol
+
+
+def test_step_d_larger_sizes(torch):
+    from oracle import stepd as D
+    for N, Np in ((128, 9), (256, 7)):
+        scan = make_scan(1, N=N, Np=Np)
+        banner(f"step D N={N} Np={Np}")
+        plan, obj, _ = run_gpu(scan, [(2, HIO, 0.9)], real=F64, n_ei=2)
+        vol = plan.assemble_volume().cpu().numpy()
+        o, _ = run_oracle(scan, [(2, HIO, 0.9)], n_ei=2)
+        ref = D.assemble_volume(o.g, scan["theta"])
+        assert rel_l2(vol, ref) <= 1e-10
+
+
+def test_deterministic_and_homogeneous(torch):
+    """Same inputs give bitwise-equal results; scaling I by 4 scales every iterate by exactly 2."""
+    scan = make_scan(1, Np=6)
+    sched = [(25, HIO, 0.9)]
+    banner("determinism / homogeneity")
+    _, a, ea = run_gpu(scan, sched, real=F32)
+    _, b, eb = run_gpu(scan, sched, real=F32)
+    assert np.array_equal(a, b) and np.array_equal(ea[0], eb[0])
+    scan4 = dict(scan, I=(scan["I"] * np.float32(4.0)))
+    _, c, ec = run_gpu(scan4, sched, real=F32)
+    assert np.array_equal(c, 2 * a)
+    assert np.array_equal(ec[0], ea[0])
+
+
+def test_host_pointer_inputs(torch):
+    scan = make_scan(1, Np=10)      # more than one staging chunk of 8
+    sched = [(3, HIO, 0.9)]
+    banner("host pointer submit")
+    _, a, _ = run_gpu(scan, sched, real=F32, device_inputs=False)
+    _, b, _ = run_gpu(scan, sched, real=F32, device_inputs=True)
+    assert np.array_equal(a, b)
+
+
+def test_fp16_amplitudes_error_is_small(torch):
+    """FP16 amplitudes with a per-angle power-of-two scale: error vs the FP64 oracle is reported and bounded."""
+    scan = make_scan(1)
+    banner("fp16 amplitudes")
+    # binary16 keeps 11 significant bits (relative step 2^-11 = 4.9e-4 per amplitude); the initial
+    # guess and every projection use the rounded amplitudes
+    for sched, lim16, lim32 in (([(1, HIO, 0.9)], 1e-2, 1e-5), ([(10, ER, 0.0)], 2e-2, 1e-4)):
+        _, a16, _ = run_gpu(scan, sched, real=F32, amp=1)
+        _, a32, _ = run_gpu(scan, sched, real=F32, amp=0)
+        o, _ = run_oracle(scan, sched)
+        r16, r32 = rel_l2(a16, o.g), rel_l2(a32, o.g)
+        print(f"{sched}: fp16-amplitude error {r16:.3e}, fp32 {r32:.3e}")
+        assert r32 <= lim32
+        assert r16 <= lim16
+
+
+def test_api_errors(torch):
+    import paper_2402_05283_amd as cp
+    scan = make_scan(1, Np=4)
+    banner("api errors")
+    plan = cp.Plan(64, 4, n_ei=5)
+    with pytest.raises(cp.CpraError) as e:
+        plan.iterate(1)
+    assert e.value.status == -4                    # nothing submitted
+    I = torch.from_numpy(scan["I"]).cuda()
+    S = torch.from_numpy(scan["support"]).cuda()
+    bad = I.clone()
+    bad[1, 3, 3] = float("nan")
+    with pytest.raises(cp.CpraError) as e:
+        plan.submit(0, bad, S)
+    assert e.value.status == -6
+    plan.submit(0, I, S)
+    with pytest.raises(cp.CpraError) as e:
+        plan.submit(1, I[1:2], S[1:2])
+    assert e.value.status == -4                    # submitted twice
+    with pytest.raises(cp.CpraError) as e:
+        plan.submit(3, I[:2], S[:2])
+    assert e.value.status == -1                    # out of range
+    plan.iterate(3)
+    with pytest.raises(cp.CpraError) as e:
+        plan.assemble_volume()
+    assert e.value.status == -4                    # not at an episode end
+    plan.iterate(2)
+    plan.assemble_volume()
