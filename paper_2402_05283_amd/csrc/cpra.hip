@@ -86,7 +86,7 @@ Layout layout_of(const cpra_params* p) {
   L.ampscale = take(Np * rs);
   L.maskw = take(Np * N * N / 8);
   L.den = take(Np * 8);
-  L.tw = take(N * cs);
+  L.tw = take((3 * N + 3 * H) * cs);   // twiddle tables (kernels.hpp, TwLayout)
   L.coup = take(Np * sizeof(cpra::Coupling));
   L.alist = take(Np * 4);
   L.errpart = take((size_t)kErrSlots * Np * col_tiles(p->N) * 8);
@@ -99,6 +99,7 @@ Layout layout_of(const cpra_params* p) {
   L.cnt_inv = take(N * N * rs);
   L.zc = stepd_chunk(p->N);
   L.plane = take((size_t)L.zc * N * N * cs);
+  L.prep_part = take(Np * cpra::kPrepBlocks * 12);
   L.total = o;
   return L;
 }
@@ -248,8 +249,11 @@ cpra_status cpra_submit_angles(cpra_plan_t pl, int32_t first, int32_t count, con
   HIPCHK(pl, hipMemsetAsync(pl->ws + pl->L.flags, 0, 4, pl->stream));
   std::vector<int32_t> ids(count);
   for (int i = 0; i < count; ++i) ids[i] = first + i;
-  for (int c0 = 0; c0 < count; c0 += kStageAngles) {
-    const int cn = std::min(kStageAngles, count - c0);
+  // host inputs are staged through the workspace a few angles at a time;
+  // device inputs go out in one launch of each kernel
+  const int chunk = ptr_kind == CPRA_PTR_HOST ? kStageAngles : count;
+  for (int c0 = 0; c0 < count; c0 += chunk) {
+    const int cn = std::min(chunk, count - c0);
     const float* dI;
     const uint8_t* dS;
     if (ptr_kind == CPRA_PTR_HOST) {
@@ -267,7 +271,7 @@ cpra_status cpra_submit_angles(cpra_plan_t pl, int32_t first, int32_t count, con
     HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist + 0, ids.data() + c0, cn * 4, hipMemcpyHostToDevice, pl->stream));
     ops.init(pl, at<int>(pl, pl->L.alist), cn, pl->cur);
     LAUNCHCHK(pl);
-    if (ptr_kind == CPRA_PTR_HOST || c0 + kStageAngles < count) HIPCHK(pl, hipStreamSynchronize(pl->stream));
+    if (ptr_kind == CPRA_PTR_HOST) HIPCHK(pl, hipStreamSynchronize(pl->stream));
   }
   int flag = 0;
   HIPCHK(pl, hipMemcpyAsync(&flag, pl->ws + pl->L.flags, 4, hipMemcpyDeviceToHost, pl->stream));

@@ -14,7 +14,7 @@ namespace cpra_impl {
 
 struct Layout {
   size_t P, Pmid, g0, g1, A2, ampscale, maskw, den, tw, coup, alist, errpart, errhist, flags, stage_I,
-      stage_S, csr_ptr, csr_ent, cnt_inv, plane, total;
+      stage_S, csr_ptr, csr_ent, cnt_inv, plane, prep_part, total;
   int zc;   // z-planes per step-D chunk
 };
 
@@ -72,21 +72,31 @@ template <int N, typename T, typename AP>
 struct Impl {
   using C = cx<T>;
   static void twiddles(cpra_plan_t pl) {
-    k_twiddles<T><<<(N + 255) / 256, 256, 0, pl->stream>>>(at<C>(pl, pl->L.tw), N);
+    k_twiddles<N, T><<<(TwLayout<N>::SIZE + 255) / 256, 256, 0, pl->stream>>>(at<C>(pl, pl->L.tw));
   }
   static void prep(cpra_plan_t pl, const float* I, const uint8_t* S, int first, int count) {
-    k_prep<N, T, AP><<<count, 256, 0, pl->stream>>>(I, S, first, at<AP>(pl, pl->L.A2), at<T>(pl, pl->L.ampscale),
-                                                    at<uint32_t>(pl, pl->L.maskw), at<double>(pl, pl->L.den),
-                                                    at<int>(pl, pl->L.flags));
+    double* psum = at<double>(pl, pl->L.prep_part);
+    float* pmax = reinterpret_cast<float*>(psum + (size_t)pl->p.Np * kPrepBlocks);
+    k_prep_stats<N><<<dim3(kPrepBlocks, count), 256, 0, pl->stream>>>(I, first, psum, pmax, at<int>(pl, pl->L.flags));
+    k_prep_final<T, AP><<<(count + 63) / 64, 64, 0, pl->stream>>>(first, count, psum, pmax, at<double>(pl, pl->L.den),
+                                                                  at<T>(pl, pl->L.ampscale));
+    k_prep_encode<N, T, AP><<<dim3(N / 8, count), 256, 0, pl->stream>>>(I, S, first, at<AP>(pl, pl->L.A2),
+                                                                        at<T>(pl, pl->L.ampscale),
+                                                                        at<uint32_t>(pl, pl->L.maskw));
   }
   // initial objects of `count` angles listed at alist (device)
   static void init(cpra_plan_t pl, const int* d_list, int count, int gbuf) {
     using CG = ColGeom<N>;
     using RG = RowGeom<N>;
     dim3 gc(CG::TILES, count), bc(CG::R1 * CG::C);
-    k_col<N, T, AP, 1, false><<<gc, bc, 0, pl->stream>>>(
-        nullptr, at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2), at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw),
-        d_list, nullptr, 0, nullptr, CG::TILES, pl->p.seed);
+    if constexpr (CG::S == 2)
+      k_col_pair<N, T, AP, 1, false><<<gc, bc, 0, pl->stream>>>(
+          nullptr, at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2), at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw),
+          d_list, nullptr, 0, nullptr, CG::TILES, pl->p.seed);
+    else
+      k_col<N, T, AP, 1, false><<<gc, bc, 0, pl->stream>>>(
+          nullptr, at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2), at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw),
+          d_list, nullptr, 0, nullptr, CG::TILES, pl->p.seed);
     T* g = at<T>(pl, gbuf ? pl->L.g1 : pl->L.g0);
     dim3 gr(N / RG::RPB, count), br(RG::T * RG::RPB);
     k_row<N, T><<<gr, br, 0, pl->stream>>>(at<C>(pl, pl->L.Pmid), at<C>(pl, pl->L.P), g, g,
@@ -104,14 +114,18 @@ struct Impl {
       e0 = pl->next_event(); e1 = pl->next_event(); e2 = pl->next_event();
       if (e0) (void)hipEventRecord(e0, pl->stream);
     }
-    if (errpart)
-      k_col<N, T, AP, 0, true><<<gc, bc, 0, pl->stream>>>(at<C>(pl, pl->L.P), at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2),
-                                                         at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw), al, cp,
-                                                         couple ? 1 : 0, errpart, CG::TILES, 0);
-    else
-      k_col<N, T, AP, 0, false><<<gc, bc, 0, pl->stream>>>(at<C>(pl, pl->L.P), at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2),
-                                                          at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw), al, cp,
-                                                          couple ? 1 : 0, nullptr, CG::TILES, 0);
+    auto launch = [&](auto kern, double* ep) {
+      kern<<<gc, bc, 0, pl->stream>>>(at<C>(pl, pl->L.P), at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2),
+                                      at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw), al, cp, couple ? 1 : 0, ep,
+                                      CG::TILES, 0);
+    };
+    if constexpr (CG::S == 2) {
+      if (errpart) launch(k_col_pair<N, T, AP, 0, true>, errpart);
+      else launch(k_col_pair<N, T, AP, 0, false>, nullptr);
+    } else {
+      if (errpart) launch(k_col<N, T, AP, 0, true>, errpart);
+      else launch(k_col<N, T, AP, 0, false>, nullptr);
+    }
     if (e1) (void)hipEventRecord(e1, pl->stream);
     T* gin = at<T>(pl, pl->cur ? pl->L.g1 : pl->L.g0);
     T* gout = couple ? at<T>(pl, pl->cur ? pl->L.g0 : pl->L.g1) : gin;

@@ -29,12 +29,14 @@ namespace cpra {
 
 // ---------------------------------------------------------------- configs
 // Column transform of length N = R1 * R2: R1 threads per column, R2 values each.
+// S > 1: the R1-point step-2 DFT is shared by S = 2 neighbouring threads
+// (an R1/2-point DFT in registers + one radix-2 butterfly across lanes).
 template <int N> struct ColCfg;
-template <> struct ColCfg<64> { static constexpr int R1 = 8, R2 = 8, C = 16; };
-template <> struct ColCfg<128> { static constexpr int R1 = 8, R2 = 16, C = 16; };
-template <> struct ColCfg<256> { static constexpr int R1 = 16, R2 = 16, C = 16; };
-template <> struct ColCfg<512> { static constexpr int R1 = 16, R2 = 32, C = 16; };
-template <> struct ColCfg<1024> { static constexpr int R1 = 32, R2 = 32, C = 8; };
+template <> struct ColCfg<64> { static constexpr int R1 = 8, R2 = 8, C = 16, S = 1; };
+template <> struct ColCfg<128> { static constexpr int R1 = 8, R2 = 16, C = 16, S = 1; };
+template <> struct ColCfg<256> { static constexpr int R1 = 16, R2 = 16, C = 16, S = 1; };
+template <> struct ColCfg<512> { static constexpr int R1 = 32, R2 = 16, C = 16, S = 2; };
+template <> struct ColCfg<1024> { static constexpr int R1 = 32, R2 = 32, C = 8, S = 1; };
 
 // Row half-spectrum transform of length L = N/2 = F1 * F2 (F1: frequency
 // residue modulus, F2: space residue modulus), T = F1/2 threads per row,
@@ -55,17 +57,21 @@ template <int N> struct RowGeom {
   static constexpr int E = 2 * F2;          // complex values per thread
   static constexpr int MW = N / (32 * T);   // mask words per thread per row
   static constexpr int PADR = 1;
+  // row stride of the LDS exchange (complex slots): >= F2 (F1 + 1) and = T mod 32,
+  // so that both access patterns of a wave touch distinct 8-byte bank pairs
+  static constexpr int RSTRIDE = F2 * (F1 + PADR) + ((T - (F2 * (F1 + PADR)) % 32) + 32) % 32;
   static_assert(F1 * F2 == L, "row decomposition");
   static_assert(F1 <= F2 && F2 % T == 0, "row ownership");
   static_assert(MW >= 1 && (N % (32 * T)) == 0, "mask words");
 };
 
 template <int N> struct ColGeom {
-  static constexpr int R1 = ColCfg<N>::R1, R2 = ColCfg<N>::R2, C = ColCfg<N>::C;
-  static constexpr int Q = R2 / R1;
-  static constexpr int PADC = 1;
+  static constexpr int R1 = ColCfg<N>::R1, R2 = ColCfg<N>::R2, C = ColCfg<N>::C, S = ColCfg<N>::S;
+  static constexpr int Q = (S == 1) ? R2 / R1 : 1;
+  static constexpr int PADC = (S == 1) ? 1 : 16;   // paired layout: slab stride = 16 mod 32 slots
   static constexpr int TILES = (N / 2) / C;
-  static_assert(R1 * R2 == N && R2 % R1 == 0 && (N / 2) % C == 0, "column decomposition");
+  static_assert(R1 * R2 == N && (N / 2) % C == 0, "column decomposition");
+  static_assert(S == 1 ? (R2 % R1 == 0) : (S == 2 && R1 / 2 == R2), "step-2 ownership");
 };
 
 // Space position of bit b of thread tau's mask words in a row: t index.
@@ -87,19 +93,28 @@ struct Coupling {   // per angle, used at episode boundaries
 template <typename AP> struct AmpIO;
 template <> struct AmpIO<float2> {
   using real = float;
+  using pair_t = float2;
+  __device__ static pair_t raw(const float2* p) { return *p; }
+  __device__ static float2 decode(pair_t v, float) { return v; }
   __device__ static float2 load(const float2* p, float) { return *p; }
 };
 template <> struct AmpIO<double2> {
   using real = double;
+  using pair_t = double2;
+  __device__ static pair_t raw(const double2* p) { return *p; }
+  __device__ static double2 decode(pair_t v, double) { return v; }
   __device__ static double2 load(const double2* p, double) { return *p; }
 };
 template <> struct AmpIO<__half2> {
   using real = float;
-  __device__ static float2 load(const __half2* p, float s) {
-    float2 v = __half22float2(*p);
+  using pair_t = __half2;
+  __device__ static pair_t raw(const __half2* p) { return *p; }
+  __device__ static float2 decode(pair_t h, float s) {
+    float2 v = __half22float2(h);
     v.x *= s; v.y *= s;
     return v;
   }
+  __device__ static float2 load(const __half2* p, float s) { return decode(*p, s); }
 };
 
 __host__ __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
@@ -110,134 +125,231 @@ __host__ __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t c) {
 }
 
 // ---------------------------------------------------------------- twiddles
-template <typename T>
-__global__ void k_twiddles(cx<T>* tw, int N) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < N) {
-    double s, c;
-    sincospi(-2.0 * (double)j / (double)N, &s, &c);
-    tw[j] = mk<cx<T>>((T)c, (T)s);
+// One FP64-generated table per plan, rounded to the working precision, laid
+// out so that every thread reads its twiddles as consecutive pairs:
+//   [0, N)            W_N^j
+//   colf [a][c]       W_N^{a c}            (column pass, forward, R1 x R2)
+//   coli [c][a]       conj W_N^{a c}       (column pass, inverse, R2 x R1)
+//   rc2r [k1][m2]     conj W_L^{k1 m2}     (row pass C2R, F1 x F2, L = N/2)
+//   rr2c [m2][k1]     W_L^{m2 k1}          (row pass R2C, F2 x F1)
+//   rpp  [k1][k2]     W_N^{k1 + F1 k2}     (row pass real/complex pre/post-processing)
+template <int N> struct TwLayout {
+  static constexpr int L = N / 2;
+  static constexpr int COLF = N, COLI = 2 * N, RC2R = 3 * N, RR2C = 3 * N + L, RPP = 3 * N + 2 * L;
+  static constexpr int SIZE = 3 * N + 3 * L;
+};
+
+template <int N, typename T>
+__global__ void k_twiddles(cx<T>* tw) {
+  using TL = TwLayout<N>;
+  constexpr int R1 = ColCfg<N>::R1, R2 = ColCfg<N>::R2, F1 = RowCfg<N>::F1, F2 = RowCfg<N>::F2;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= TL::SIZE) return;
+  long e;          // exponent of W_N (exp(-2 pi i e / N))
+  bool cj = false;
+  if (i < TL::COLF) {
+    e = i;
+  } else if (i < TL::COLI) {
+    const int r = i - TL::COLF; e = (long)(r / R2) * (r % R2);
+  } else if (i < TL::RC2R) {
+    // coli [c][a-slot]: a = slot (S = 1) or a = s + 2 a' with slot = s R1/2 + a' (S = 2)
+    const int r = i - TL::COLI, c = r / R1, slot = r % R1;
+    const int aa = (ColCfg<N>::S == 1) ? slot : (slot / (R1 / 2)) + 2 * (slot % (R1 / 2));
+    e = (long)c * aa; cj = true;
+  } else if (i < TL::RR2C) {
+    const int r = i - TL::RC2R; e = 2L * (r / F2) * (r % F2); cj = true;
+  } else if (i < TL::RPP) {
+    const int r = i - TL::RR2C; e = 2L * (r / F1) * (r % F1);
+  } else {
+    const int r = i - TL::RPP; e = (r / F2) + (long)F1 * (r % F2);
   }
+  e %= N;
+  double s, c;
+  sincospi(-2.0 * (double)e / (double)N, &s, &c);
+  tw[i] = mk<cx<T>>((T)c, (T)(cj ? -s : s));
+}
+
+// two consecutive complex values (16-byte load for FP32)
+__device__ __forceinline__ void load_pair(const float2* p, float2& a, float2& b) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  a = make_float2(v.x, v.y);
+  b = make_float2(v.z, v.w);
+}
+__device__ __forceinline__ void load_pair(const double2* p, double2& a, double2& b) {
+  a = p[0];
+  b = p[1];
 }
 
 // ---------------------------------------------------------------- prep
-// One block per submitted angle: amplitude pairs, support bits, sum A^2.
-template <int N, typename T, typename AP>
-__global__ void __launch_bounds__(256) k_prep(const float* __restrict__ I, const uint8_t* __restrict__ sup,
-                                              int first, AP* __restrict__ A2, T* __restrict__ ampscale,
-                                              uint32_t* __restrict__ maskw, double* __restrict__ den,
-                                              int* __restrict__ flags) {
-  using G = RowGeom<N>;
-  constexpr int H = N / 2;
-  const int n = first + blockIdx.x;
-  const float* In = I + (size_t)blockIdx.x * N * N;
-  const uint8_t* Sn = sup + (size_t)blockIdx.x * N * N;
+// Input preparation in three launches over all submitted angles:
+//   k_prep_stats  : per (angle, 1/16 of the map) partial sum of I >= 0 (FP64),
+//                   max sqrt(I), NaN/Inf flag
+//   k_prep_final  : per angle, fixed-order sum -> den = sum A^2, binary16 scale
+//   k_prep_encode : amplitude pairs (A(q), A(-q)) in native order and the
+//                   support bits in the row pass's thread order
+constexpr int kPrepBlocks = 16;
+
+template <int N>
+__global__ void __launch_bounds__(256) k_prep_stats(const float* __restrict__ I, int first, double* __restrict__ psum,
+                                                    float* __restrict__ pmax, int* __restrict__ flags) {
   __shared__ double red[256];
   __shared__ float redm[256];
+  __shared__ int redb[256];
+  const int b = blockIdx.x, idx = blockIdx.y;
+  const float* In = I + (size_t)idx * N * N;
+  constexpr int per = N * N / kPrepBlocks;
   double acc = 0.0;
   float amax = 0.f;
   int bad = 0;
-  for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
-    float v = In[i];
+  for (int i = b * per + threadIdx.x; i < (b + 1) * per; i += blockDim.x) {
+    const float v = In[i];
     if (!isfinite(v)) bad = 1;
     if (v >= 0.f) { acc += (double)v; amax = fmaxf(amax, sqrtf(v)); }
   }
   red[threadIdx.x] = acc;
   redm[threadIdx.x] = amax;
+  redb[threadIdx.x] = bad;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+    if ((int)threadIdx.x < s) {
       red[threadIdx.x] += red[threadIdx.x + s];
       redm[threadIdx.x] = fmaxf(redm[threadIdx.x], redm[threadIdx.x + s]);
+      redb[threadIdx.x] |= redb[threadIdx.x + s];
     }
     __syncthreads();
   }
-  if (bad) atomicOr(flags, 1);
-  if (threadIdx.x == 0) den[n] = red[0];
-  float scale = 1.f;
+  if (threadIdx.x == 0) {
+    const int n = first + idx;
+    psum[(size_t)n * kPrepBlocks + b] = red[0];
+    pmax[(size_t)n * kPrepBlocks + b] = redm[0];
+    if (redb[0]) atomicOr(flags, 1);
+  }
+}
+
+template <typename T, typename AP>
+__global__ void k_prep_final(int first, int count, const double* __restrict__ psum, const float* __restrict__ pmax,
+                             double* __restrict__ den, T* __restrict__ ampscale) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int n = first + i;
+  double s = 0.0;
+  float m = 0.f;
+  for (int b = 0; b < kPrepBlocks; ++b) {
+    s += psum[(size_t)n * kPrepBlocks + b];
+    m = fmaxf(m, pmax[(size_t)n * kPrepBlocks + b]);
+  }
+  den[n] = s;
   if constexpr (std::is_same<AP, __half2>::value) {
     int e = 0;
-    frexpf(redm[0] > 0.f ? redm[0] : 1.f, &e);   // max A < 2^e
-    scale = ldexpf(1.f, e - 14);                  // stored values < 2^14
-    if (threadIdx.x == 0) ampscale[n] = scale;
+    frexpf(m > 0.f ? m : 1.f, &e);   // max A < 2^e
+    ampscale[n] = ldexpf(1.f, e - 14);   // stored values < 2^14
   } else {
-    if (threadIdx.x == 0) ampscale[n] = (T)1;
+    ampscale[n] = (T)1;
   }
-  const float inv = 1.f / scale;
-  auto amp = [&](int wn, int un) -> float {       // native (w, u) -> A, -1 if unmeasured
-    float v = In[((wn + H) % N) * N + ((un + H) % N)];
+}
+
+template <int N, typename T, typename AP>
+__global__ void __launch_bounds__(256) k_prep_encode(const float* __restrict__ I, const uint8_t* __restrict__ sup,
+                                                     int first, AP* __restrict__ A2, const T* __restrict__ ampscale,
+                                                     uint32_t* __restrict__ maskw) {
+  using G = RowGeom<N>;
+  constexpr int H = N / 2, ROWS = 8;
+  const int idx = blockIdx.y;
+  const int n = first + idx;
+  const int r0 = blockIdx.x * ROWS;
+  const float* In = I + (size_t)idx * N * N;
+  const uint8_t* Sn = sup + (size_t)idx * N * N;
+  auto ampf = [&](int wn, int un) -> float {       // native (w, u) -> A, -1 if unmeasured
+    const float v = In[((wn + H) % N) * N + ((un + H) % N)];
     return v >= 0.f ? sqrtf(v) : -1.f;
   };
   auto ampd = [&](int wn, int un) -> double {
-    float v = In[((wn + H) % N) * N + ((un + H) % N)];
+    const float v = In[((wn + H) % N) * N + ((un + H) % N)];
     return v >= 0.f ? sqrt((double)v) : -1.0;
   };
   AP* An = A2 + (size_t)n * N * H;
-  for (int i = threadIdx.x; i < N * H; i += blockDim.x) {
-    int w = i / H, j = i % H;
-    int wm = (N - w) % N;
+  for (int i = threadIdx.x; i < ROWS * H; i += blockDim.x) {
+    const int w = r0 + i / H, j = i % H;
+    const int wm = (N - w) % N;
     if constexpr (std::is_same<AP, double2>::value) {
       double a, b;
       if (j == 0) { a = ampd(w, 0); b = ampd(w, H); }
       else { a = ampd(w, j); b = ampd(wm, N - j); }
-      An[i] = make_double2(a, b);
+      An[(size_t)w * H + j] = make_double2(a, b);
     } else {
       float a, b;
-      if (j == 0) { a = amp(w, 0); b = amp(w, H); }
-      else { a = amp(w, j); b = amp(wm, N - j); }
+      if (j == 0) { a = ampf(w, 0); b = ampf(w, H); }
+      else { a = ampf(w, j); b = ampf(wm, N - j); }
       if constexpr (std::is_same<AP, __half2>::value) {
-        An[i] = __floats2half2_rn(a >= 0.f ? a * inv : -1.f, b >= 0.f ? b * inv : -1.f);
+        const float inv = 1.f / (float)ampscale[n];    // power of two: exact
+        An[(size_t)w * H + j] = __floats2half2_rn(a >= 0.f ? a * inv : -1.f, b >= 0.f ? b * inv : -1.f);
       } else {
-        An[i] = make_float2(a, b);
+        An[(size_t)w * H + j] = make_float2(a, b);
       }
     }
   }
   uint32_t* Mn = maskw + (size_t)n * N * G::T * G::MW;
-  for (int i = threadIdx.x; i < N * G::T * G::MW; i += blockDim.x) {
-    int z = i / (G::T * G::MW);
-    int r = i % (G::T * G::MW);
-    int tau = r / G::MW, wd = r % G::MW;
+  for (int i = threadIdx.x; i < ROWS * G::T * G::MW; i += blockDim.x) {
+    const int z = r0 + i / (G::T * G::MW);
+    const int r = i % (G::T * G::MW);
+    const int tau = r / G::MW, wd = r % G::MW;
     uint32_t word = 0;
     for (int b = 0; b < 32; ++b) {
-      int t = mask_bit_t<N>(tau, wd * 32 + b);
+      const int t = mask_bit_t<N>(tau, wd * 32 + b);
       if (Sn[z * N + t]) word |= (1u << b);
     }
-    Mn[i] = word;
+    Mn[(size_t)z * G::T * G::MW + r] = word;
   }
 }
 
 // ---------------------------------------------------------------- column pass
-// Modulus projection of one value with its two amplitudes (q and -q).
-template <typename T, bool ERR>
-__device__ __forceinline__ cx<T> project2(cx<T> G, T a1, T a2, bool neg, T scale, double& err) {
-  T mag2 = G.x * G.x + G.y * G.y;
-  T mag = sqrt(mag2);
-  T inv = mag > (T)0 ? (T)1 / mag : (T)0;
-  T sg = neg ? (T)-1 : (T)1;
-  cx<T> p1 = a1 >= (T)0 ? (mag > (T)0 ? cscale(G, a1 * inv) : mk<cx<T>>(a1 * sg, (T)0)) : G;
-  cx<T> p2 = a2 >= (T)0 ? (mag > (T)0 ? cscale(G, a2 * inv) : mk<cx<T>>(a2 * sg, (T)0)) : G;
-  if constexpr (ERR) {
-    if (a1 >= (T)0) { double d = (double)mag - (double)a1; err += d * d; }
-    if (a2 >= (T)0) { double d = (double)mag - (double)a2; err += d * d; }
-  }
-  return cscale(cadd(p1, p2), scale);
-}
+// Modulus projection of one Fourier value G with the amplitudes of q and -q
+// (Hermitian part of the projected spectrum), scaled by `scale` (1/(2N^2)).
+// a < 0 marks an unmeasured pixel (G kept); G = 0 takes the zero-phase value
+// with the sign (-1)^(w+u) of the centred origin (`neg`).  `ew` weights the
+// error terms (1/2 for the self-paired columns, whose -q is also in the column).
+template <typename T> struct Proj;
 
-// Single-amplitude version (used for the self-paired columns 0 and N/2).
-template <typename T, bool ERR>
-__device__ __forceinline__ cx<T> project1(cx<T> G, T a, bool neg, double& err) {
-  T mag = sqrt(G.x * G.x + G.y * G.y);
-  T sg = neg ? (T)-1 : (T)1;
-  if constexpr (ERR) {
-    if (a >= (T)0) { double d = (double)mag - (double)a; err += d * d; }
+template <> struct Proj<float> {
+  template <bool ERR>
+  static __device__ __forceinline__ float2 two(float2 G, float a1, float a2, bool neg, float scale, double& err,
+                                               double ew) {
+    const float m2 = fmaf(G.x, G.x, G.y * G.y);
+    const bool nz = m2 >= 1.17549435e-38f;          // |G|^2 normal: rsq is exact to ~1 ulp there
+    const float r = __builtin_amdgcn_rsqf(m2);       // 1/|G|
+    const bool u1 = a1 >= 0.f, u2 = a2 >= 0.f;
+    const float s = ((u1 ? a1 * r : 1.f) + (u2 ? a2 * r : 1.f)) * scale;
+    const float z = ((u1 ? a1 : 0.f) + (u2 ? a2 : 0.f)) * (neg ? -scale : scale);
+    if constexpr (ERR) {
+      const double mag = nz ? (double)(m2 * r) : 0.0;
+      const double d1 = mag - (double)a1, d2 = mag - (double)a2;
+      err += ew * ((u1 ? d1 * d1 : 0.0) + (u2 ? d2 * d2 : 0.0));
+    }
+    return make_float2(nz ? G.x * s : z, nz ? G.y * s : 0.f);
   }
-  if (a < (T)0) return G;
-  return mag > (T)0 ? cscale(G, a / mag) : mk<cx<T>>(a * sg, (T)0);
-}
+};
 
-template <int N, typename T>
+template <> struct Proj<double> {
+  template <bool ERR>
+  static __device__ __forceinline__ double2 two(double2 G, double a1, double a2, bool neg, double scale, double& err,
+                                                double ew) {
+    const double mag = sqrt(G.x * G.x + G.y * G.y);
+    const bool nz = mag > 0.0;
+    const double inv = nz ? 1.0 / mag : 0.0;
+    const bool u1 = a1 >= 0.0, u2 = a2 >= 0.0;
+    const double s = ((u1 ? a1 * inv : 1.0) + (u2 ? a2 * inv : 1.0)) * scale;
+    const double z = ((u1 ? a1 : 0.0) + (u2 ? a2 : 0.0)) * (neg ? -scale : scale);
+    if constexpr (ERR) {
+      const double d1 = mag - a1, d2 = mag - a2;
+      err += ew * ((u1 ? d1 * d1 : 0.0) + (u2 ? d2 * d2 : 0.0));
+    }
+    return make_double2(nz ? G.x * s : z, nz ? G.y * s : 0.0);
+  }
+};
+
+template <int N, typename T, int NT = 256>
 __device__ __forceinline__ void block_reduce_store(double v, double* out) {
-  __shared__ double red[256];
+  __shared__ double red[NT];
   const int nt = blockDim.x;
   red[threadIdx.x] = v;
   __syncthreads();
@@ -248,9 +360,11 @@ __device__ __forceinline__ void block_reduce_store(double v, double* out) {
   if (threadIdx.x == 0) *out = red[0];
 }
 
-// Column pass.  MODE 0: iteration (read P, optionally coupled; FFT_z;
-// error; modulus projection; IFFT_z; write Pmid).  MODE 1: initial guess
-// (generate the Hermitian part of A e^{i phi}, IFFT_z, write Pmid).
+// Column pass.  One workgroup = C packed columns x N rows of one angle;
+// R1 threads per column, R2 values each (four-step FFT along z).
+// MODE 0: iteration (read P, optionally coupled; FFT_z; error; modulus
+// projection; IFFT_z; write Pmid).  MODE 1: initial guess (generate the
+// Hermitian part of (-1)^(w+u) A e^{i phi} / N^2, IFFT_z, write Pmid).
 template <int N, typename T, typename AP, int MODE, bool ERR>
 __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
     k_col(const cx<T>* __restrict__ P, cx<T>* __restrict__ Pmid, const AP* __restrict__ A2,
@@ -258,6 +372,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
           const Coupling* __restrict__ coup, int couple, double* __restrict__ errpart, int ntiles,
           uint64_t seed) {
   using Gm = ColGeom<N>;
+  using TL = TwLayout<N>;
   using C = cx<T>;
   constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::C, Q = Gm::Q, H = N / 2;
   constexpr int LSTRIDE = R1 * CC + Gm::PADC;     // per c-slab
@@ -272,35 +387,59 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
   const int j = j0 + col;
   const size_t plane = (size_t)N * H;
   const T scale = (T)0.5 / ((T)N * (T)N);
+  const AP* An = A2 + (size_t)n * plane;
+  const T as = ampscale[n];
   double err = 0.0;
-  C g[R2];   // holds [q][d] after the forward transform (Q*R1 == R2)
+  C g[R2];   // [q][d] after the forward transform (Q * R1 == R2)
 
   if constexpr (MODE == 0) {
     C v[R2];
     const C* Pn = P + (size_t)n * plane;
-#pragma unroll
-    for (int b = 0; b < R2; ++b) v[b] = Pn[(size_t)(a + R1 * b) * H + j];
+    sfor<0, R2>([&](auto bv) CPRA_INLINE {
+      constexpr int b = decltype(bv)::value;
+      v[b] = Pn[(size_t)(a + R1 * b) * H + j];
+    });
+    // amplitude pairs of the values this thread will hold after the forward
+    // transform (w = a + R1 q + R2 d), fetched now so both HBM streams overlap
+    constexpr bool PREFETCH = R2 <= 16;
+    typename AmpIO<AP>::pair_t amp[PREFETCH ? R2 : 1];
+    if (PREFETCH && j0 != 0) {
+      sfor<0, R2>([&](auto iv) CPRA_INLINE {
+        constexpr int i = decltype(iv)::value;
+        constexpr int q = i / R1, d = i % R1;
+        if constexpr (PREFETCH) amp[i] = AmpIO<AP>::raw(An + (size_t)(a + R1 * q + R2 * d) * H + j);
+      });
+    }
     if (couple) {
       const Coupling cp = coup[n];
       const T wl = (T)cp.wl, w0 = (T)cp.w0, wr = (T)cp.wr;
       const C* Pl = P + (size_t)cp.left * plane;
       const C* Pr = P + (size_t)cp.right * plane;
-      const bool ml = cp.mirror_left && j != 0, mr = cp.mirror_right && j != 0;
-#pragma unroll
-      for (int b = 0; b < R2; ++b) {
-        C l = Pl[(size_t)(a + R1 * b) * H + j];
-        C r = Pr[(size_t)(a + R1 * b) * H + j];
-        if (ml) l.y = -l.y;
-        if (mr) r.y = -r.y;
-        v[b] = mk<C>(w0 * v[b].x + wl * l.x + wr * r.x, w0 * v[b].y + wl * l.y + wr * r.y);
-      }
+      // the seam mirror t -> -t conjugates a real row's spectrum; the packed
+      // DC/Nyquist column (both real) is unchanged
+      const T sl = (cp.mirror_left && j != 0) ? (T)-1 : (T)1;
+      const T sr = (cp.mirror_right && j != 0) ? (T)-1 : (T)1;
+      sfor<0, R2>([&](auto bv) CPRA_INLINE {
+        constexpr int b = decltype(bv)::value;
+        const C l = Pl[(size_t)(a + R1 * b) * H + j];
+        const C r = Pr[(size_t)(a + R1 * b) * H + j];
+        v[b] = mk<C>(w0 * v[b].x + wl * l.x + wr * r.x, w0 * v[b].y + (wl * sl) * l.y + (wr * sr) * r.y);
+      });
     }
     // forward step 1: R2-point DFT over b, twiddle W_N^{a c}
     dft<R2, -1>(v);
-#pragma unroll
-    for (int c = 1; c < R2; ++c) v[c] = cmul(v[c], tw[(a * c) & (N - 1)]);
-#pragma unroll
-    for (int c = 0; c < R2; ++c) lds[c * LSTRIDE + a * CC + col] = v[c];
+    const C* tf = tw + TL::COLF + a * R2;
+    sfor<0, R2 / 2>([&](auto iv) CPRA_INLINE {
+      constexpr int c = 2 * decltype(iv)::value;
+      C t0, t1;
+      load_pair(tf + c, t0, t1);
+      if (c != 0) v[c] = cmul(v[c], t0);
+      v[c + 1] = cmul(v[c + 1], t1);
+    });
+    sfor<0, R2>([&](auto cv) CPRA_INLINE {
+      constexpr int c = decltype(cv)::value;
+      lds[c * LSTRIDE + a * CC + col] = v[c];
+    });
     __syncthreads();
     // forward step 2: for c = a + R1 q, R1-point DFT over a' -> G[c + R2 d]
     sfor<0, Q>([&](auto qv) CPRA_INLINE {
@@ -313,10 +452,21 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
       dft<R1, -1>(g + q * R1);
     });
     // modulus projection
-    const AP* An = A2 + (size_t)n * plane;
-    const T as = ampscale[n];
-    if (j0 == 0) {
-      // packed column 0 (DC and Nyquist columns): pair Z[w] with Z[-w]
+    if (j0 != 0) {
+      sfor<0, R2>([&](auto iv) CPRA_INLINE {
+        constexpr int i = decltype(iv)::value;
+        constexpr int q = i / R1, d = i % R1;
+        const int w = a + R1 * q + R2 * d;
+        typename AmpIO<AP>::pair_t raw;
+        if constexpr (PREFETCH) raw = amp[i];
+        else raw = AmpIO<AP>::raw(An + (size_t)w * H + j);
+        const auto pa = AmpIO<AP>::decode(raw, as);
+        g[i] = Proj<T>::template two<ERR>(g[i], (T)pa.x, (T)pa.y, ((w + j) & 1) != 0, scale, err, 1.0);
+      });
+    } else {
+      // tile 0 holds the packed column 0 = DC + i * Nyquist column: split
+      // Z[w] into Ga = (Z[w] + conj Z[-w])/2 and Gb = (Z[w] - conj Z[-w])/(2i)
+      // (pairing w with -w through LDS), project each, and pack again
       __syncthreads();
       if (col == 0) {
         sfor<0, R2>([&](auto iv) CPRA_INLINE {
@@ -326,44 +476,32 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
         });
       }
       __syncthreads();
-    }
-    sfor<0, R2>([&](auto iv) CPRA_INLINE {
-      constexpr int i = decltype(iv)::value;
-      constexpr int q = i / R1, d = i % R1;
-      {
-        const int c = a + R1 * q;
-        const int w = c + R2 * d;
-        C Gv = g[i];
+      sfor<0, R2>([&](auto iv) CPRA_INLINE {
+        constexpr int i = decltype(iv)::value;
+        constexpr int q = i / R1, d = i % R1;
+        const int w = a + R1 * q + R2 * d;
         if (j != 0) {
-          auto pa = AmpIO<AP>::load(An + (size_t)w * H + j, as);
-          g[i] = project2<T, ERR>(Gv, (T)pa.x, (T)pa.y, ((w + j) & 1) != 0, scale, err);
+          const auto pa = AmpIO<AP>::load(An + (size_t)w * H + j, as);
+          g[i] = Proj<T>::template two<ERR>(g[i], (T)pa.x, (T)pa.y, ((w + j) & 1) != 0, scale, err, 1.0);
         } else {
           const int wm = (N - w) & (N - 1);
-          C Zm = zl[wm];
-          // Ga = (Z + conj Zm)/2, Gb = (Z - conj Zm)/(2i)
-          C Ga = mk<C>((T)0.5 * (Gv.x + Zm.x), (T)0.5 * (Gv.y - Zm.y));
-          C Gb = mk<C>((T)0.5 * (Gv.y + Zm.y), (T)0.5 * (Zm.x - Gv.x));
-          auto p0 = AmpIO<AP>::load(An + (size_t)w * H, as);     // (A(w,0), A(w,N/2))
-          auto pm = AmpIO<AP>::load(An + (size_t)wm * H, as);    // (A(-w,0), A(-w,N/2))
-          double e1 = 0.0, e2 = 0.0;
-          C a1 = project1<T, ERR>(Ga, (T)p0.x, (w & 1) != 0, e1);
-          C a2 = project1<T, false>(Ga, (T)pm.x, (w & 1) != 0, e2);
-          C b1 = project1<T, ERR>(Gb, (T)p0.y, ((w + H) & 1) != 0, e1);
-          C b2 = project1<T, false>(Gb, (T)pm.y, ((w + H) & 1) != 0, e2);
-          if constexpr (ERR) err += e1;
-          C Gah = cscale(cadd(a1, a2), scale);
-          C Gbh = cscale(cadd(b1, b2), scale);
-          g[i] = mk<C>(Gah.x - Gbh.y, Gah.y + Gbh.x);   // Ga + i Gb
+          const C Z = g[i], Zm = zl[wm];
+          const C Ga = mk<C>((T)0.5 * (Z.x + Zm.x), (T)0.5 * (Z.y - Zm.y));
+          const C Gb = mk<C>((T)0.5 * (Z.y + Zm.y), (T)0.5 * (Zm.x - Z.x));
+          const auto p0 = AmpIO<AP>::load(An + (size_t)w * H, as);     // (A(w,0), A(w,N/2))
+          const auto pm = AmpIO<AP>::load(An + (size_t)wm * H, as);    // (A(-w,0), A(-w,N/2))
+          // each of w, -w is visited once per column: half weight on the paired error terms
+          const C Pa = Proj<T>::template two<ERR>(Ga, (T)p0.x, (T)pm.x, (w & 1) != 0, scale, err, 0.5);
+          const C Pb = Proj<T>::template two<ERR>(Gb, (T)p0.y, (T)pm.y, ((w + H) & 1) != 0, scale, err, 0.5);
+          g[i] = mk<C>(Pa.x - Pb.y, Pa.y + Pb.x);   // Ga'' + i Gb''
         }
-      }
-    });
+      });
+    }
   } else {
     // initial guess: Hermitian part of (-1)^{w+u} A e^{i phi}, scaled by 1/N^2
-    const AP* An = A2 + (size_t)n * plane;
-    const T as = ampscale[n];
-    auto phase = [&](int w, int u) -> C {
-      uint64_t cnt = ((uint64_t)n * N + (uint64_t)w) * N + (uint64_t)u;
-      uint64_t r = splitmix64_at(seed, cnt) >> 40;
+    auto phase = [&](int w, int u) CPRA_INLINE -> C {
+      const uint64_t cnt = ((uint64_t)n * N + (uint64_t)w) * N + (uint64_t)u;
+      const uint64_t r = splitmix64_at(seed, cnt) >> 40;
       double s, c;
       sincospi(2.0 * (double)r / 16777216.0, &s, &c);
       return mk<C>((T)c, (T)s);
@@ -371,31 +509,28 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
     sfor<0, R2>([&](auto iv) CPRA_INLINE {
       constexpr int i = decltype(iv)::value;
       constexpr int q = i / R1, d = i % R1;
-      {
-        const int c = a + R1 * q;
-        const int w = c + R2 * d;
-        const int wm = (N - w) & (N - 1);
-        C out;
-        if (j != 0) {
-          auto pa = AmpIO<AP>::load(An + (size_t)w * H + j, as);
-          T a1 = pa.x > (T)0 ? (T)pa.x : (T)0, a2 = pa.y > (T)0 ? (T)pa.y : (T)0;
-          C e1 = phase(w, j), e2 = conj(phase(wm, N - j));
-          T sg = ((w + j) & 1) ? -scale : scale;
-          out = mk<C>(sg * (a1 * e1.x + a2 * e2.x), sg * (a1 * e1.y + a2 * e2.y));
-        } else {
-          auto p0 = AmpIO<AP>::load(An + (size_t)w * H, as);
-          auto pm = AmpIO<AP>::load(An + (size_t)wm * H, as);
-          T a0 = p0.x > 0 ? (T)p0.x : (T)0, am0 = pm.x > 0 ? (T)pm.x : (T)0;
-          T aH = p0.y > 0 ? (T)p0.y : (T)0, amH = pm.y > 0 ? (T)pm.y : (T)0;
-          C e1 = phase(w, 0), e2 = conj(phase(wm, 0));
-          C f1 = phase(w, H), f2 = conj(phase(wm, H));
-          T sa = (w & 1) ? -scale : scale, sb = ((w + H) & 1) ? -scale : scale;
-          C Ga = mk<C>(sa * (a0 * e1.x + am0 * e2.x), sa * (a0 * e1.y + am0 * e2.y));
-          C Gb = mk<C>(sb * (aH * f1.x + amH * f2.x), sb * (aH * f1.y + amH * f2.y));
-          out = mk<C>(Ga.x - Gb.y, Ga.y + Gb.x);
-        }
-        g[i] = out;
+      const int w = a + R1 * q + R2 * d;
+      const int wm = (N - w) & (N - 1);
+      C out;
+      if (j != 0) {
+        const auto pa = AmpIO<AP>::load(An + (size_t)w * H + j, as);
+        const T a1 = pa.x > (T)0 ? (T)pa.x : (T)0, a2 = pa.y > (T)0 ? (T)pa.y : (T)0;
+        const C e1 = phase(w, j), e2 = conj(phase(wm, N - j));
+        const T sg = ((w + j) & 1) ? -scale : scale;
+        out = mk<C>(sg * (a1 * e1.x + a2 * e2.x), sg * (a1 * e1.y + a2 * e2.y));
+      } else {
+        const auto p0 = AmpIO<AP>::load(An + (size_t)w * H, as);
+        const auto pm = AmpIO<AP>::load(An + (size_t)wm * H, as);
+        const T a0 = p0.x > 0 ? (T)p0.x : (T)0, am0 = pm.x > 0 ? (T)pm.x : (T)0;
+        const T aH = p0.y > 0 ? (T)p0.y : (T)0, amH = pm.y > 0 ? (T)pm.y : (T)0;
+        const C e1 = phase(w, 0), e2 = conj(phase(wm, 0));
+        const C f1 = phase(w, H), f2 = conj(phase(wm, H));
+        const T sa = (w & 1) ? -scale : scale, sb = ((w + H) & 1) ? -scale : scale;
+        const C Ga = mk<C>(sa * (a0 * e1.x + am0 * e2.x), sa * (a0 * e1.y + am0 * e2.y));
+        const C Gb = mk<C>(sb * (aH * f1.x + amH * f2.x), sb * (aH * f1.y + amH * f2.y));
+        out = mk<C>(Ga.x - Gb.y, Ga.y + Gb.x);
       }
+      g[i] = out;
     });
   }
 
@@ -405,26 +540,238 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
     constexpr int q = decltype(qv)::value;
     const int c = a + R1 * q;
     dft<R1, +1>(g + q * R1);
-    sfor<0, R1>([&](auto av) CPRA_INLINE {
-      constexpr int ap = decltype(av)::value;
-      C t = g[q * R1 + ap];
-      if (ap != 0) t = cmulc(t, tw[(ap * c) & (N - 1)]);
-      lds[c * LSTRIDE + ap * CC + col] = t;
+    const C* ti = tw + TL::COLI + c * R1;
+    sfor<0, R1 / 2>([&](auto iv) CPRA_INLINE {
+      constexpr int ap = 2 * decltype(iv)::value;
+      C t0, t1;
+      load_pair(ti + ap, t0, t1);
+      C x0 = g[q * R1 + ap], x1 = cmul(g[q * R1 + ap + 1], t1);
+      if (ap != 0) x0 = cmul(x0, t0);
+      lds[c * LSTRIDE + ap * CC + col] = x0;
+      lds[c * LSTRIDE + (ap + 1) * CC + col] = x1;
     });
   });
   __syncthreads();
   // inverse step 2: thread a gathers all c, R2-point IDFT -> s[a + R1 b]
   {
     C v[R2];
-#pragma unroll
-    for (int c = 0; c < R2; ++c) v[c] = lds[c * LSTRIDE + a * CC + col];
+    sfor<0, R2>([&](auto cv) CPRA_INLINE {
+      constexpr int c = decltype(cv)::value;
+      v[c] = lds[c * LSTRIDE + a * CC + col];
+    });
     dft<R2, +1>(v);
     C* Mn = Pmid + (size_t)n * plane;
-#pragma unroll
-    for (int b = 0; b < R2; ++b) Mn[(size_t)(a + R1 * b) * H + j] = v[b];
+    sfor<0, R2>([&](auto bv) CPRA_INLINE {
+      constexpr int b = decltype(bv)::value;
+      Mn[(size_t)(a + R1 * b) * H + j] = v[b];
+    });
   }
   if constexpr (MODE == 0 && ERR) {
     block_reduce_store<N, T>(err, errpart + (size_t)ai * ntiles + tile);
+  }
+}
+
+// Column pass with paired step-2 DFTs (S = 2): R1 = 2 R2 threads per column,
+// R2 values each.  Step 1 as in k_col; in step 2 thread a owns c = a/2 and
+// half s = a%2 of the R1-point DFT over a: an R2-point DFT over the a of its
+// parity, a W_R1^{s k'} twiddle and a radix-2 butterfly with its partner
+// lane (a ^ 1, i.e. lane ^ C).  It then holds G[w] for w = c + R2 (k' + R2 s).
+// The inverse mirrors it.  Same modes and outputs as k_col.
+template <typename T>
+__device__ __forceinline__ cx<T> xor_lane(cx<T> v, int mask) {
+  return mk<cx<T>>(__shfl_xor(v.x, mask), __shfl_xor(v.y, mask));
+}
+
+template <int N, typename T, typename AP, int MODE, bool ERR>
+__global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((amdgpu_waves_per_eu(4)))
+    k_col_pair(const cx<T>* __restrict__ P, cx<T>* __restrict__ Pmid, const AP* __restrict__ A2,
+               const T* __restrict__ ampscale, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
+               const Coupling* __restrict__ coup, int couple, double* __restrict__ errpart, int ntiles,
+               uint64_t seed) {
+  using Gm = ColGeom<N>;
+  using TL = TwLayout<N>;
+  using C = cx<T>;
+  constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::C, H = N / 2, NT = R1 * CC;
+  constexpr int LSTRIDE = R1 * CC + Gm::PADC;
+  static_assert(Gm::S == 2, "paired kernel");
+  __shared__ C lds[R2 * LSTRIDE];
+  __shared__ C zl[(MODE == 0) ? N : 1];
+  const int col = threadIdx.x % CC;
+  const int a = threadIdx.x / CC;          // row residue in step 1
+  const int c = a >> 1, sh = a & 1;        // step 2: owned c and half
+  const int tile = blockIdx.x;
+  const int ai = blockIdx.y;
+  const int n = alist[ai];
+  const int j0 = tile * CC;
+  const int j = j0 + col;
+  const size_t plane = (size_t)N * H;
+  const T scale = (T)0.5 / ((T)N * (T)N);
+  const AP* An = A2 + (size_t)n * plane;
+  const T as = ampscale[n];
+  double err = 0.0;
+  C g[R2];   // after the forward transform: G[c + R2 (k' + R2 sh)] at index k'
+
+  if constexpr (MODE == 0) {
+    C v[R2];
+    const C* Pn = P + (size_t)n * plane;
+    sfor<0, R2>([&](auto bv) CPRA_INLINE {
+      constexpr int b = decltype(bv)::value;
+      v[b] = Pn[(size_t)(a + R1 * b) * H + j];
+    });
+    typename AmpIO<AP>::pair_t amp[R2];
+    if (j0 != 0) {
+      sfor<0, R2>([&](auto kv) CPRA_INLINE {
+        constexpr int k = decltype(kv)::value;
+        amp[k] = AmpIO<AP>::raw(An + (size_t)(c + R2 * (k + R2 * sh)) * H + j);
+      });
+    }
+    if (couple) {
+      const Coupling cp = coup[n];
+      const T wl = (T)cp.wl, w0 = (T)cp.w0, wr = (T)cp.wr;
+      const C* Pl = P + (size_t)cp.left * plane;
+      const C* Pr = P + (size_t)cp.right * plane;
+      const T sl = (cp.mirror_left && j != 0) ? (T)-1 : (T)1;
+      const T sr = (cp.mirror_right && j != 0) ? (T)-1 : (T)1;
+      sfor<0, R2>([&](auto bv) CPRA_INLINE {
+        constexpr int b = decltype(bv)::value;
+        const C l = Pl[(size_t)(a + R1 * b) * H + j];
+        const C r = Pr[(size_t)(a + R1 * b) * H + j];
+        v[b] = mk<C>(w0 * v[b].x + wl * l.x + wr * r.x, w0 * v[b].y + (wl * sl) * l.y + (wr * sr) * r.y);
+      });
+    }
+    // forward step 1: R2-point DFT over b, twiddle W_N^{a c'}
+    dft<R2, -1>(v);
+    const C* tf = tw + TL::COLF + a * R2;
+    sfor<0, R2 / 2>([&](auto iv) CPRA_INLINE {
+      constexpr int cc = 2 * decltype(iv)::value;
+      C t0, t1;
+      load_pair(tf + cc, t0, t1);
+      if (cc != 0) v[cc] = cmul(v[cc], t0);
+      v[cc + 1] = cmul(v[cc + 1], t1);
+    });
+    sfor<0, R2>([&](auto cv) CPRA_INLINE {
+      constexpr int cc = decltype(cv)::value;
+      lds[cc * LSTRIDE + a * CC + col] = v[cc];
+    });
+    __syncthreads();
+    // forward step 2: half sh of the R1-point DFT over a for this c
+    sfor<0, R2>([&](auto kv) CPRA_INLINE {
+      constexpr int k = decltype(kv)::value;
+      g[k] = lds[c * LSTRIDE + (sh + 2 * k) * CC + col];
+    });
+    dft<R2, -1>(g);
+    sfor<0, R2>([&](auto kv) CPRA_INLINE {
+      constexpr int k = decltype(kv)::value;
+      const C t = sh ? twc<-1, k, R1>(g[k]) : g[k];
+      const C o = xor_lane<T>(t, CC);
+      g[k] = sh ? csub(o, t) : cadd(t, o);
+    });
+    // modulus projection
+    if (j0 != 0) {
+      sfor<0, R2>([&](auto kv) CPRA_INLINE {
+        constexpr int k = decltype(kv)::value;
+        const int w = c + R2 * (k + R2 * sh);
+        const auto pa = AmpIO<AP>::decode(amp[k], as);
+        g[k] = Proj<T>::template two<ERR>(g[k], (T)pa.x, (T)pa.y, ((w + j) & 1) != 0, scale, err, 1.0);
+      });
+    } else {
+      __syncthreads();
+      if (col == 0) {
+        sfor<0, R2>([&](auto kv) CPRA_INLINE {
+          constexpr int k = decltype(kv)::value;
+          zl[c + R2 * (k + R2 * sh)] = g[k];
+        });
+      }
+      __syncthreads();
+      sfor<0, R2>([&](auto kv) CPRA_INLINE {
+        constexpr int k = decltype(kv)::value;
+        const int w = c + R2 * (k + R2 * sh);
+        if (j != 0) {
+          const auto pa = AmpIO<AP>::load(An + (size_t)w * H + j, as);
+          g[k] = Proj<T>::template two<ERR>(g[k], (T)pa.x, (T)pa.y, ((w + j) & 1) != 0, scale, err, 1.0);
+        } else {
+          const int wm = (N - w) & (N - 1);
+          const C Z = g[k], Zm = zl[wm];
+          const C Ga = mk<C>((T)0.5 * (Z.x + Zm.x), (T)0.5 * (Z.y - Zm.y));
+          const C Gb = mk<C>((T)0.5 * (Z.y + Zm.y), (T)0.5 * (Zm.x - Z.x));
+          const auto p0 = AmpIO<AP>::load(An + (size_t)w * H, as);
+          const auto pm = AmpIO<AP>::load(An + (size_t)wm * H, as);
+          const C Pa = Proj<T>::template two<ERR>(Ga, (T)p0.x, (T)pm.x, (w & 1) != 0, scale, err, 0.5);
+          const C Pb = Proj<T>::template two<ERR>(Gb, (T)p0.y, (T)pm.y, ((w + H) & 1) != 0, scale, err, 0.5);
+          g[k] = mk<C>(Pa.x - Pb.y, Pa.y + Pb.x);
+        }
+      });
+    }
+  } else {
+    auto phase = [&](int w, int u) CPRA_INLINE -> C {
+      const uint64_t cnt = ((uint64_t)n * N + (uint64_t)w) * N + (uint64_t)u;
+      const uint64_t r = splitmix64_at(seed, cnt) >> 40;
+      double s, co;
+      sincospi(2.0 * (double)r / 16777216.0, &s, &co);
+      return mk<C>((T)co, (T)s);
+    };
+    sfor<0, R2>([&](auto kv) CPRA_INLINE {
+      constexpr int k = decltype(kv)::value;
+      const int w = c + R2 * (k + R2 * sh);
+      const int wm = (N - w) & (N - 1);
+      C out;
+      if (j != 0) {
+        const auto pa = AmpIO<AP>::load(An + (size_t)w * H + j, as);
+        const T a1 = pa.x > (T)0 ? (T)pa.x : (T)0, a2 = pa.y > (T)0 ? (T)pa.y : (T)0;
+        const C e1 = phase(w, j), e2 = conj(phase(wm, N - j));
+        const T sg = ((w + j) & 1) ? -scale : scale;
+        out = mk<C>(sg * (a1 * e1.x + a2 * e2.x), sg * (a1 * e1.y + a2 * e2.y));
+      } else {
+        const auto p0 = AmpIO<AP>::load(An + (size_t)w * H, as);
+        const auto pm = AmpIO<AP>::load(An + (size_t)wm * H, as);
+        const T a0 = p0.x > 0 ? (T)p0.x : (T)0, am0 = pm.x > 0 ? (T)pm.x : (T)0;
+        const T aH = p0.y > 0 ? (T)p0.y : (T)0, amH = pm.y > 0 ? (T)pm.y : (T)0;
+        const C e1 = phase(w, 0), e2 = conj(phase(wm, 0));
+        const C f1 = phase(w, H), f2 = conj(phase(wm, H));
+        const T sa = (w & 1) ? -scale : scale, sb = ((w + H) & 1) ? -scale : scale;
+        const C Ga = mk<C>(sa * (a0 * e1.x + am0 * e2.x), sa * (a0 * e1.y + am0 * e2.y));
+        const C Gb = mk<C>(sb * (aH * f1.x + amH * f2.x), sb * (aH * f1.y + amH * f2.y));
+        out = mk<C>(Ga.x - Gb.y, Ga.y + Gb.x);
+      }
+      g[k] = out;
+    });
+  }
+
+  // inverse: radix-2 butterfly across the lane pair, W_R1^{-sh k'}, R2-point IDFT over k'
+  if constexpr (MODE == 0) __syncthreads();   // all forward reads of lds are done
+  sfor<0, R2>([&](auto kv) CPRA_INLINE {
+    constexpr int k = decltype(kv)::value;
+    const C o = xor_lane<T>(g[k], CC);
+    const C u = sh ? csub(o, g[k]) : cadd(g[k], o);
+    g[k] = sh ? twc<+1, k, R1>(u) : u;
+  });
+  dft<R2, +1>(g);   // g[a'] = Y'[c][sh + 2 a']
+  {
+    const C* ti = tw + TL::COLI + c * R1 + sh * R2;   // conj W_N^{(sh + 2a') c}
+    sfor<0, R2 / 2>([&](auto iv) CPRA_INLINE {
+      constexpr int k = 2 * decltype(iv)::value;
+      C t0, t1;
+      load_pair(ti + k, t0, t1);
+      lds[c * LSTRIDE + (sh + 2 * k) * CC + col] = cmul(g[k], t0);
+      lds[c * LSTRIDE + (sh + 2 * (k + 1)) * CC + col] = cmul(g[k + 1], t1);
+    });
+  }
+  __syncthreads();
+  {
+    C v[R2];
+    sfor<0, R2>([&](auto cv) CPRA_INLINE {
+      constexpr int cc = decltype(cv)::value;
+      v[cc] = lds[cc * LSTRIDE + a * CC + col];
+    });
+    dft<R2, +1>(v);
+    C* Mn = Pmid + (size_t)n * plane;
+    sfor<0, R2>([&](auto bv) CPRA_INLINE {
+      constexpr int b = decltype(bv)::value;
+      Mn[(size_t)(a + R1 * b) * H + j] = v[b];
+    });
+  }
+  if constexpr (MODE == 0 && ERR) {
+    block_reduce_store<N, T, NT>(err, errpart + (size_t)ai * ntiles + tile);
   }
 }
 
@@ -438,18 +785,31 @@ __global__ void __launch_bounds__(RowCfg<N>::F1 / 2 * RowCfg<N>::RPB)
           const uint32_t* __restrict__ maskw, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
           const Coupling* __restrict__ coup, int couple, int mode, T beta, int positivity) {
   using Gm = RowGeom<N>;
+  using TL = TwLayout<N>;
   using C = cx<T>;
   constexpr int F1 = Gm::F1, F2 = Gm::F2, TT = Gm::T, SPT = Gm::SPT, H = N / 2;
   constexpr int RPB = Gm::RPB, MW = Gm::MW;
   constexpr int LS = F1 + Gm::PADR;       // lds stride per m2
-  __shared__ C lds[RPB * F2 * LS];
+  __shared__ C lds[RPB * Gm::RSTRIDE];
   const int tau = threadIdx.x % TT;
   const int r = threadIdx.x / TT;
   const int n = alist[blockIdx.y];
   const int z = blockIdx.x * RPB + r;
-  C* L0 = lds + r * F2 * LS;
+  C* L0 = lds + r * Gm::RSTRIDE;
   const size_t rowc = ((size_t)n * N + z) * H;     // complex row base
   const size_t rowr = ((size_t)n * N + z) * N;     // real row base
+  // the current iterate of this thread's pixels, fetched up front so that
+  // its HBM latency overlaps the Pmid stream (not needed for ER/estimate)
+  C gk[SPT][F1];
+  if (mode == 1) {
+    sfor<0, SPT>([&](auto jv) CPRA_INLINE {
+      constexpr int jj = decltype(jv)::value;
+      sfor<0, F1>([&](auto mv) CPRA_INLINE {
+        constexpr int m1 = decltype(mv)::value;
+        gk[jj][m1] = *reinterpret_cast<const C*>(gin + rowr + 2 * (tau + TT * jj + F2 * m1));
+      });
+    });
+  }
   const bool t0 = (tau == 0);
   // owned frequency classes: {tau, F1 - tau}, or {0, F1/2} for tau = 0
   const int k1v[2] = {t0 ? 0 : tau, t0 ? F1 / 2 : F1 - tau};
@@ -477,22 +837,23 @@ __global__ void __launch_bounds__(RowCfg<N>::F1 / 2 * RowCfg<N>::RPB)
   });
   sfor<0, 2>([&](auto ss) CPRA_INLINE {
     constexpr int s = decltype(ss)::value;
-    sfor<0, F2>([&](auto kk) CPRA_INLINE {
-      constexpr int k2 = decltype(kk)::value;
-      // partner L - k of k = k1 + F1 k2 lives in this thread
-      constexpr int pk_t0 = (s == 0) ? ((F2 - k2) % F2) : (F2 - 1 - k2);
-      const C a = f[s][k2];
-      const C pa = f[s][pk_t0], pb = f[1 - s][F2 - 1 - k2];
-      const C pv = mk<C>(t0 ? pa.x : pb.x, t0 ? pa.y : pb.y);
-      const int k = k1v[s] + F1 * k2;
-      if (k == 0) {
-        x[s][k2] = mk<C>(a.x + a.y, a.x - a.y);
-      } else {
+    const C* tp = tw + TL::RPP + k1v[s] * F2;         // W_N^{k1 + F1 k2}, k2 = 0..F2-1
+    sfor<0, F2 / 2>([&](auto kk) CPRA_INLINE {
+      C tpair[2];
+      load_pair(tp + 2 * decltype(kk)::value, tpair[0], tpair[1]);
+      sfor<0, 2>([&](auto hh) CPRA_INLINE {
+        constexpr int k2 = 2 * decltype(kk)::value + decltype(hh)::value;
+        // partner L - k of k = k1 + F1 k2 lives in this thread
+        constexpr int pk_t0 = (s == 0) ? ((F2 - k2) % F2) : (F2 - 1 - k2);
+        const C a = f[s][k2];
+        const C pa = f[s][pk_t0], pb = f[1 - s][F2 - 1 - k2];
+        const C pv = mk<C>(t0 ? pa.x : pb.x, t0 ? pa.y : pb.y);
+        const bool k0 = (s == 0 && k2 == 0) && t0;     // k == 0: packed DC and Nyquist
         const C b = conj(pv);
         const C sum = cadd(a, b), dif = csub(a, b);
-        const C t = cmulc(dif, tw[k]);                 // (a - b) e^{+2 pi i k/N}
-        x[s][k2] = mk<C>(sum.x - t.y, sum.y + t.x);    // sum + i t
-      }
+        const C t = cmulc(dif, tpair[decltype(hh)::value]);   // (a - b) e^{+2 pi i k/N}
+        x[s][k2] = k0 ? mk<C>(a.x + a.y, a.x - a.y) : mk<C>(sum.x - t.y, sum.y + t.x);   // sum + i t
+      });
     });
   });
   // ---- C2R step 1: F2-point IDFT over k2, twiddle e^{+2 pi i k1 m2 / L}, to LDS
@@ -500,11 +861,15 @@ __global__ void __launch_bounds__(RowCfg<N>::F1 / 2 * RowCfg<N>::RPB)
     constexpr int s = decltype(ss)::value;
     dft<F2, +1>(x[s]);
     const int k1 = k1v[s];
-    sfor<0, F2>([&](auto mm) CPRA_INLINE {
-      constexpr int m2 = decltype(mm)::value;
-      C v = x[s][m2];
-      if (m2 != 0) v = cmulc(v, tw[(2 * k1 * m2) & (N - 1)]);
-      L0[m2 * LS + k1] = v;
+    const C* tp = tw + TL::RC2R + k1 * F2;            // e^{+2 pi i k1 m2 / L}
+    sfor<0, F2 / 2>([&](auto mm) CPRA_INLINE {
+      constexpr int m2 = 2 * decltype(mm)::value;
+      C t0w, t1w;
+      load_pair(tp + m2, t0w, t1w);
+      C v0 = x[s][m2];
+      if (m2 != 0) v0 = cmul(v0, t0w);
+      L0[m2 * LS + k1] = v0;
+      L0[(m2 + 1) * LS + k1] = cmul(x[s][m2 + 1], t1w);
     });
   });
   __syncthreads();
@@ -544,16 +909,16 @@ __global__ void __launch_bounds__(RowCfg<N>::F1 / 2 * RowCfg<N>::RPB)
         if (mode == 2) {
           out = mk<C>(g0 ? gp.x : (T)0, g1 ? gp.y : (T)0);
         } else {
-          C gk = *reinterpret_cast<const C*>(gin + rowr + 2 * m);
+          C gkv = gk[jj][m1];
           if (couple) {
             C lv, rv;
             if (cp.mirror_left) lv = mk<C>(gl[(N - 2 * m) & (N - 1)], gl[N - 1 - 2 * m]);
             else lv = *reinterpret_cast<const C*>(gl + 2 * m);
             if (cp.mirror_right) rv = mk<C>(gr[(N - 2 * m) & (N - 1)], gr[N - 1 - 2 * m]);
             else rv = *reinterpret_cast<const C*>(gr + 2 * m);
-            gk = mk<C>(w0 * gk.x + wl * lv.x + wr * rv.x, w0 * gk.y + wl * lv.y + wr * rv.y);
+            gkv = mk<C>(w0 * gkv.x + wl * lv.x + wr * rv.x, w0 * gkv.y + wl * lv.y + wr * rv.y);
           }
-          out = mk<C>(g0 ? gp.x : gk.x - beta * gp.x, g1 ? gp.y : gk.y - beta * gp.y);
+          out = mk<C>(g0 ? gp.x : gkv.x - beta * gp.x, g1 ? gp.y : gkv.y - beta * gp.y);
         }
       }
       *reinterpret_cast<C*>(gout + rowr + 2 * m) = out;
@@ -568,11 +933,15 @@ __global__ void __launch_bounds__(RowCfg<N>::F1 / 2 * RowCfg<N>::RPB)
     constexpr int jj = decltype(jv)::value;
     const int m2 = tau + TT * jj;
     dft<F1, -1>(sp[jj]);
-    sfor<0, F1>([&](auto kv) CPRA_INLINE {
-      constexpr int k1 = decltype(kv)::value;
-      C v = sp[jj][k1];
-      if (k1 != 0) v = cmul(v, tw[(2 * k1 * m2) & (N - 1)]);
-      L0[m2 * LS + k1] = v;
+    const C* tp = tw + TL::RR2C + m2 * F1;            // e^{-2 pi i m2 k1 / L}
+    sfor<0, F1 / 2>([&](auto kv) CPRA_INLINE {
+      constexpr int k1 = 2 * decltype(kv)::value;
+      C t0w, t1w;
+      load_pair(tp + k1, t0w, t1w);
+      C v0 = sp[jj][k1];
+      if (k1 != 0) v0 = cmul(v0, t0w);
+      L0[m2 * LS + k1] = v0;
+      L0[m2 * LS + k1 + 1] = cmul(sp[jj][k1 + 1], t1w);
     });
   });
   __syncthreads();
@@ -589,22 +958,23 @@ __global__ void __launch_bounds__(RowCfg<N>::F1 / 2 * RowCfg<N>::RPB)
   // ---- post-processing to the packed half spectrum, store
   sfor<0, 2>([&](auto ss) CPRA_INLINE {
     constexpr int s = decltype(ss)::value;
-    sfor<0, F2>([&](auto kk) CPRA_INLINE {
-      constexpr int k2 = decltype(kk)::value;
-      constexpr int pk_t0 = (s == 0) ? ((F2 - k2) % F2) : (F2 - 1 - k2);
-      const C Z = x[s][k2];
-      const C za = x[s][pk_t0], zb = x[1 - s][F2 - 1 - k2];
-      const C Zp = mk<C>(t0 ? za.x : zb.x, t0 ? za.y : zb.y);
-      const int k = k1v[s] + F1 * k2;
-      C o;
-      if (k == 0) {
-        o = mk<C>(Z.x + Z.y, Z.x - Z.y);
-      } else {
+    const int k1 = k1v[s];
+    const C* tp = tw + TL::RPP + k1 * F2;             // W_N^{k1 + F1 k2}
+    sfor<0, F2 / 2>([&](auto kk) CPRA_INLINE {
+      C tpair[2];
+      load_pair(tp + 2 * decltype(kk)::value, tpair[0], tpair[1]);
+      sfor<0, 2>([&](auto hh) CPRA_INLINE {
+        constexpr int k2 = 2 * decltype(kk)::value + decltype(hh)::value;
+        constexpr int pk_t0 = (s == 0) ? ((F2 - k2) % F2) : (F2 - 1 - k2);
+        const C Z = x[s][k2];
+        const C za = x[s][pk_t0], zb = x[1 - s][F2 - 1 - k2];
+        const C Zp = mk<C>(t0 ? za.x : zb.x, t0 ? za.y : zb.y);
+        const bool k0 = (s == 0 && k2 == 0) && t0;
         const C Fe = mk<C>((T)0.5 * (Z.x + Zp.x), (T)0.5 * (Z.y - Zp.y));
         const C Fo = mk<C>((T)0.5 * (Z.y + Zp.y), (T)0.5 * (Zp.x - Z.x));
-        o = cadd(Fe, cmul(Fo, tw[k]));
-      }
-      P[rowc + k] = o;
+        const C o = cadd(Fe, cmul(Fo, tpair[decltype(hh)::value]));
+        P[rowc + k1 + F1 * k2] = k0 ? mk<C>(Z.x + Z.y, Z.x - Z.y) : o;
+      });
     });
   });
 }
