@@ -44,6 +44,16 @@ int col_tiles(int N) {
 
 int stepd_chunk(int N) { return N >= 512 ? 32 : N; }
 
+size_t mask_words_per_row(int N) {
+  switch (N) {
+    case 64: return RowGeom<64>::T * RowGeom<64>::MW;
+    case 128: return RowGeom<128>::T * RowGeom<128>::MW;
+    case 256: return RowGeom<256>::T * RowGeom<256>::MW;
+    case 512: return RowGeom<512>::T * RowGeom<512>::MW;
+    default: return RowGeom<1024>::T * RowGeom<1024>::MW;
+  }
+}
+
 cpra_status validate(const cpra_params* p, std::string& msg) {
   if (!p) { msg = "params is NULL"; return CPRA_ERR_ARG; }
   if (p->struct_size != sizeof(cpra_params)) { msg = "params.struct_size mismatch"; return CPRA_ERR_ARG; }
@@ -84,7 +94,7 @@ Layout layout_of(const cpra_params* p) {
   L.g1 = take(Np * N * N * rs);
   L.A2 = take(Np * N * H * aps);
   L.ampscale = take(Np * rs);
-  L.maskw = take(Np * N * N / 8);
+  L.maskw = take(Np * N * mask_words_per_row(p->N) * 4);
   L.den = take(Np * 8);
   L.tw = take((3 * N + 3 * H) * cs);   // twiddle tables (kernels.hpp, TwLayout)
   L.coup = take(Np * sizeof(cpra::Coupling));

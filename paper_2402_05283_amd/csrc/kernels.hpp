@@ -39,30 +39,31 @@ template <> struct ColCfg<512> { static constexpr int R1 = 32, R2 = 16, C = 16, 
 template <> struct ColCfg<1024> { static constexpr int R1 = 32, R2 = 32, C = 8, S = 1; };
 
 // Row half-spectrum transform of length L = N/2 = F1 * F2 (F1: frequency
-// residue modulus, F2: space residue modulus), T = F1/2 threads per row,
-// each owning the frequency classes {t, F1-t} ({0, F1/2} for t = 0), so that
-// the real-to-complex pairing k <-> L-k stays inside a thread.
+// residue modulus, F2: space residue modulus).  T = F1 threads per row:
+// thread t owns frequency class k1 = t (F2 values) and the space classes
+// m2 = t + F1 jj (F2 values in all).  The real/complex pairing k <-> L-k
+// pairs class t with class (F1 - t) mod F1, i.e. lane (F1 - t) mod F1 of the
+// row group, reached with DPP lane moves.
 template <int N> struct RowCfg;
-template <> struct RowCfg<64> { static constexpr int F1 = 4, F2 = 8, RPB = 64; };
-template <> struct RowCfg<128> { static constexpr int F1 = 8, F2 = 8, RPB = 32; };
-template <> struct RowCfg<256> { static constexpr int F1 = 8, F2 = 16, RPB = 32; };
+template <> struct RowCfg<64> { static constexpr int F1 = 4, F2 = 8, RPB = 32; };
+template <> struct RowCfg<128> { static constexpr int F1 = 8, F2 = 8, RPB = 16; };
+template <> struct RowCfg<256> { static constexpr int F1 = 8, F2 = 16, RPB = 16; };
 template <> struct RowCfg<512> { static constexpr int F1 = 16, F2 = 16, RPB = 16; };
 template <> struct RowCfg<1024> { static constexpr int F1 = 16, F2 = 32, RPB = 16; };
 
 template <int N> struct RowGeom {
   static constexpr int L = N / 2;
   static constexpr int F1 = RowCfg<N>::F1, F2 = RowCfg<N>::F2, RPB = RowCfg<N>::RPB;
-  static constexpr int T = F1 / 2;          // threads per row
+  static constexpr int T = F1;              // threads per row
   static constexpr int SPT = F2 / T;        // space classes per thread
-  static constexpr int E = 2 * F2;          // complex values per thread
-  static constexpr int MW = N / (32 * T);   // mask words per thread per row
+  static constexpr int BITS = 2 * F2;       // support bits per thread per row
+  static constexpr int MW = (BITS + 31) / 32;   // mask words per thread per row
   static constexpr int PADR = 1;
   // row stride of the LDS exchange (complex slots): >= F2 (F1 + 1) and = T mod 32,
   // so that both access patterns of a wave touch distinct 8-byte bank pairs
   static constexpr int RSTRIDE = F2 * (F1 + PADR) + ((T - (F2 * (F1 + PADR)) % 32) + 32) % 32;
   static_assert(F1 * F2 == L, "row decomposition");
-  static_assert(F1 <= F2 && F2 % T == 0, "row ownership");
-  static_assert(MW >= 1 && (N % (32 * T)) == 0, "mask words");
+  static_assert(F1 <= F2 && F2 % T == 0 && (F1 == 4 || F1 == 8 || F1 == 16), "row ownership");
 };
 
 template <int N> struct ColGeom {
@@ -74,9 +75,10 @@ template <int N> struct ColGeom {
   static_assert(S == 1 ? (R2 % R1 == 0) : (S == 2 && R1 / 2 == R2), "step-2 ownership");
 };
 
-// Space position of bit b of thread tau's mask words in a row: t index.
+// Space position (t index) of support bit b of thread tau in a row; -1 past the last bit.
 template <int N> __host__ __device__ inline int mask_bit_t(int tau, int b) {
   using G = RowGeom<N>;
+  if (b >= G::BITS) return -1;
   int e = b & 1, q = b >> 1;
   int j = q / G::F1, m1 = q % G::F1;
   int m = tau + G::T * j + G::F2 * m1;
@@ -296,7 +298,7 @@ __global__ void __launch_bounds__(256) k_prep_encode(const float* __restrict__ I
     uint32_t word = 0;
     for (int b = 0; b < 32; ++b) {
       const int t = mask_bit_t<N>(tau, wd * 32 + b);
-      if (Sn[z * N + t]) word |= (1u << b);
+      if (t >= 0 && Sn[z * N + t]) word |= (1u << b);
     }
     Mn[(size_t)z * G::T * G::MW + r] = word;
   }
@@ -776,11 +778,46 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
 }
 
 // ---------------------------------------------------------------- row pass
+// Value of lane (F1 - t) mod F1 of this lane's group of F1 lanes (t = lane
+// mod F1); lanes t = 0 and t = F1/2 get an unspecified value (they pair with
+// themselves and never use it).
+template <int F1>
+__device__ __forceinline__ float partner_lane(float v) {
+  const int x = __float_as_int(v);
+  int y;
+  if constexpr (F1 == 16) {
+    y = __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false);   // row_mirror: 15 - t
+    y = __builtin_amdgcn_update_dpp(0, y, 0x111, 0xF, 0xF, false);   // row_shr:1 -> 16 - t
+  } else if constexpr (F1 == 8) {
+    y = __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);   // row_half_mirror: 7 - t
+    y = __builtin_amdgcn_update_dpp(0, y, 0x111, 0xF, 0xF, false);   // row_shr:1 -> 8 - t
+  } else {
+    static_assert(F1 == 4, "partner_lane");
+    y = __builtin_amdgcn_update_dpp(0, x, 0x6C, 0xF, 0xF, false);    // quad_perm [0,3,2,1]
+  }
+  return __int_as_float(y);
+}
+__device__ __forceinline__ double partner_lane_d(double v, int lane_src) {
+  return __shfl(v, lane_src);
+}
+template <int F1, typename C>
+__device__ __forceinline__ C partner_c(C v, int partner_lane_idx) {
+  if constexpr (std::is_same<C, float2>::value) {
+    return make_float2(partner_lane<F1>(v.x), partner_lane<F1>(v.y));
+  } else {
+    return make_double2(partner_lane_d(v.x, partner_lane_idx), partner_lane_d(v.y, partner_lane_idx));
+  }
+}
+
+// Row pass over RPB rows of one angle, F1 threads per row.
 // MODE 0: initial guess (g <- g'); 1: HIO; 2: ER / episode estimate;
 // 3: reload (P <- F_t(g) from the iterate in gin; Pmid unused, g unchanged).
-// All register-array loops are compile-time (sfor) so the arrays stay in VGPRs.
+// Per row: C2R of Pmid (pre-processing, F2-point IDFT, twiddle, LDS
+// exchange, F1-point IDFT) -> g' in the space layout; real-space update with
+// the support bits and g; R2C back (F1-point DFT, twiddle, LDS exchange,
+// F2-point DFT, post-processing) -> P.
 template <int N, typename T>
-__global__ void __launch_bounds__(RowCfg<N>::F1 / 2 * RowCfg<N>::RPB)
+__global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((amdgpu_waves_per_eu(4)))
     k_row(const cx<T>* __restrict__ Pmid, cx<T>* __restrict__ P, const T* gin, T* gout,
           const uint32_t* __restrict__ maskw, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
           const Coupling* __restrict__ coup, int couple, int mode, T beta, int positivity) {
@@ -791,15 +828,18 @@ __global__ void __launch_bounds__(RowCfg<N>::F1 / 2 * RowCfg<N>::RPB)
   constexpr int RPB = Gm::RPB, MW = Gm::MW;
   constexpr int LS = F1 + Gm::PADR;       // lds stride per m2
   __shared__ C lds[RPB * Gm::RSTRIDE];
-  const int tau = threadIdx.x % TT;
+  const int tau = threadIdx.x % TT;       // owned frequency class k1 = tau
   const int r = threadIdx.x / TT;
   const int n = alist[blockIdx.y];
   const int z = blockIdx.x * RPB + r;
   C* L0 = lds + r * Gm::RSTRIDE;
   const size_t rowc = ((size_t)n * N + z) * H;     // complex row base
   const size_t rowr = ((size_t)n * N + z) * N;     // real row base
+  const bool t0 = (tau == 0);
+  const int plane_lane = (threadIdx.x & ~(TT - 1)) + ((TT - tau) & (TT - 1));   // partner, for __shfl
+
   // the current iterate of this thread's pixels, fetched up front so that
-  // its HBM latency overlaps the Pmid stream (not needed for ER/estimate)
+  // its HBM latency overlaps the Pmid stream (HIO only)
   C gk[SPT][F1];
   if (mode == 1) {
     sfor<0, SPT>([&](auto jv) CPRA_INLINE {
@@ -810,134 +850,123 @@ __global__ void __launch_bounds__(RowCfg<N>::F1 / 2 * RowCfg<N>::RPB)
       });
     });
   }
-  const bool t0 = (tau == 0);
-  // owned frequency classes: {tau, F1 - tau}, or {0, F1/2} for tau = 0
-  const int k1v[2] = {t0 ? 0 : tau, t0 ? F1 / 2 : F1 - tau};
-
   C sp[SPT][F1];
-  C x[2][F2];
+  C x[F2];
   if (mode == 3) {
     sfor<0, SPT>([&](auto jv) CPRA_INLINE {
       constexpr int jj = decltype(jv)::value;
       sfor<0, F1>([&](auto mv) CPRA_INLINE {
         constexpr int m1 = decltype(mv)::value;
-        const int m = tau + TT * jj + F2 * m1;
-        sp[jj][m1] = *reinterpret_cast<const C*>(gin + rowr + 2 * m);
+        sp[jj][m1] = *reinterpret_cast<const C*>(gin + rowr + 2 * (tau + TT * jj + F2 * m1));
       });
     });
   } else {
-  // ---- load Pmid row (frequency layout) and C2R pre-processing
-  C f[2][F2];
-  sfor<0, 2>([&](auto ss) CPRA_INLINE {
-    constexpr int s = decltype(ss)::value;
+    // ---- load Pmid class tau, C2R pre-processing:
+    //   X'[k] = (a + b) + i (a - b) e^{+2 pi i k/N},  a = T[k], b = conj T[L-k]
+    // (k = 0: a, b = the packed real DC and Nyquist values)
     sfor<0, F2>([&](auto kk) CPRA_INLINE {
       constexpr int k2 = decltype(kk)::value;
-      f[s][k2] = Pmid[rowc + k1v[s] + F1 * k2];
+      x[k2] = Pmid[rowc + tau + F1 * k2];
     });
-  });
-  sfor<0, 2>([&](auto ss) CPRA_INLINE {
-    constexpr int s = decltype(ss)::value;
-    const C* tp = tw + TL::RPP + k1v[s] * F2;         // W_N^{k1 + F1 k2}, k2 = 0..F2-1
+    C pv[F2];
+    sfor<0, F2>([&](auto kk) CPRA_INLINE {
+      constexpr int k2 = decltype(kk)::value;
+      const C other = partner_c<F1>(x[F2 - 1 - k2], plane_lane);   // partner lane, index F2-1-k2
+      const C self0 = x[(F2 - k2) % F2];                            // class 0 pairs with itself
+      pv[k2] = t0 ? self0 : other;
+    });
+    const C* tp = tw + TL::RPP + tau * F2;             // W_N^{k1 + F1 k2}
     sfor<0, F2 / 2>([&](auto kk) CPRA_INLINE {
       C tpair[2];
       load_pair(tp + 2 * decltype(kk)::value, tpair[0], tpair[1]);
       sfor<0, 2>([&](auto hh) CPRA_INLINE {
         constexpr int k2 = 2 * decltype(kk)::value + decltype(hh)::value;
-        // partner L - k of k = k1 + F1 k2 lives in this thread
-        constexpr int pk_t0 = (s == 0) ? ((F2 - k2) % F2) : (F2 - 1 - k2);
-        const C a = f[s][k2];
-        const C pa = f[s][pk_t0], pb = f[1 - s][F2 - 1 - k2];
-        const C pv = mk<C>(t0 ? pa.x : pb.x, t0 ? pa.y : pb.y);
-        const bool k0 = (s == 0 && k2 == 0) && t0;     // k == 0: packed DC and Nyquist
-        const C b = conj(pv);
+        const C a = x[k2];
+        const C b = conj(pv[k2]);
         const C sum = cadd(a, b), dif = csub(a, b);
         const C t = cmulc(dif, tpair[decltype(hh)::value]);   // (a - b) e^{+2 pi i k/N}
-        x[s][k2] = k0 ? mk<C>(a.x + a.y, a.x - a.y) : mk<C>(sum.x - t.y, sum.y + t.x);   // sum + i t
+        const bool k0 = (k2 == 0) && t0;
+        x[k2] = k0 ? mk<C>(a.x + a.y, a.x - a.y) : mk<C>(sum.x - t.y, sum.y + t.x);
       });
     });
-  });
-  // ---- C2R step 1: F2-point IDFT over k2, twiddle e^{+2 pi i k1 m2 / L}, to LDS
-  sfor<0, 2>([&](auto ss) CPRA_INLINE {
-    constexpr int s = decltype(ss)::value;
-    dft<F2, +1>(x[s]);
-    const int k1 = k1v[s];
-    const C* tp = tw + TL::RC2R + k1 * F2;            // e^{+2 pi i k1 m2 / L}
-    sfor<0, F2 / 2>([&](auto mm) CPRA_INLINE {
-      constexpr int m2 = 2 * decltype(mm)::value;
-      C t0w, t1w;
-      load_pair(tp + m2, t0w, t1w);
-      C v0 = x[s][m2];
-      if (m2 != 0) v0 = cmul(v0, t0w);
-      L0[m2 * LS + k1] = v0;
-      L0[(m2 + 1) * LS + k1] = cmul(x[s][m2 + 1], t1w);
+    // ---- C2R step 1: F2-point IDFT over k2, twiddle e^{+2 pi i k1 m2 / L}, to LDS
+    dft<F2, +1>(x);
+    {
+      const C* tq = tw + TL::RC2R + tau * F2;
+      sfor<0, F2 / 2>([&](auto mm) CPRA_INLINE {
+        constexpr int m2 = 2 * decltype(mm)::value;
+        C t0w, t1w;
+        load_pair(tq + m2, t0w, t1w);
+        C v0 = x[m2];
+        if (m2 != 0) v0 = cmul(v0, t0w);
+        L0[m2 * LS + tau] = v0;
+        L0[(m2 + 1) * LS + tau] = cmul(x[m2 + 1], t1w);
+      });
+    }
+    __syncthreads();
+    // ---- C2R step 2: for owned m2, F1-point IDFT over k1 -> x[m2 + F2 m1]
+    sfor<0, SPT>([&](auto jv) CPRA_INLINE {
+      constexpr int jj = decltype(jv)::value;
+      const int m2 = tau + TT * jj;
+      sfor<0, F1>([&](auto kv) CPRA_INLINE {
+        constexpr int k1 = decltype(kv)::value;
+        sp[jj][k1] = L0[m2 * LS + k1];
+      });
+      dft<F1, +1>(sp[jj]);
     });
-  });
-  __syncthreads();
-  // ---- C2R step 2: for owned m2, F1-point IDFT over k1 -> x[m2 + F2 m1]
-  sfor<0, SPT>([&](auto jv) CPRA_INLINE {
-    constexpr int jj = decltype(jv)::value;
-    const int m2 = tau + TT * jj;
-    sfor<0, F1>([&](auto kv) CPRA_INLINE {
-      constexpr int k1 = decltype(kv)::value;
-      sp[jj][k1] = L0[m2 * LS + k1];
-    });
-    dft<F1, +1>(sp[jj]);
-  });
-  // ---- real-space update (pixels t = 2m and 2m+1 of x[m])
-  if (mode != 3) {
-  uint32_t mwd[MW];
-  const uint32_t* Mrow = maskw + (((size_t)n * N + z) * TT + tau) * MW;
-  sfor<0, MW>([&](auto iv) CPRA_INLINE { mwd[decltype(iv)::value] = Mrow[decltype(iv)::value]; });
-  Coupling cp{};
-  if (couple) cp = coup[n];
-  const T* gl = gin + ((size_t)cp.left * N + z) * N;
-  const T* gr = gin + ((size_t)cp.right * N + z) * N;
-  const T wl = (T)cp.wl, w0 = (T)cp.w0, wr = (T)cp.wr;
-  sfor<0, SPT>([&](auto jv) CPRA_INLINE {
-    constexpr int jj = decltype(jv)::value;
-    sfor<0, F1>([&](auto mv) CPRA_INLINE {
-      constexpr int m1 = decltype(mv)::value;
-      const int m = tau + TT * jj + F2 * m1;
-      const C gp = sp[jj][m1];                      // (g'[2m], g'[2m+1])
-      C out = gp;
-      if (mode != 0) {
-        constexpr int b0 = (jj * F1 + m1) * 2;
-        const bool s0 = (mwd[b0 >> 5] >> (b0 & 31)) & 1u;
-        const bool s1 = (mwd[(b0 + 1) >> 5] >> ((b0 + 1) & 31)) & 1u;
-        const bool g0 = s0 && (!positivity || gp.x >= (T)0);
-        const bool g1 = s1 && (!positivity || gp.y >= (T)0);
-        if (mode == 2) {
-          out = mk<C>(g0 ? gp.x : (T)0, g1 ? gp.y : (T)0);
-        } else {
-          C gkv = gk[jj][m1];
-          if (couple) {
-            C lv, rv;
-            if (cp.mirror_left) lv = mk<C>(gl[(N - 2 * m) & (N - 1)], gl[N - 1 - 2 * m]);
-            else lv = *reinterpret_cast<const C*>(gl + 2 * m);
-            if (cp.mirror_right) rv = mk<C>(gr[(N - 2 * m) & (N - 1)], gr[N - 1 - 2 * m]);
-            else rv = *reinterpret_cast<const C*>(gr + 2 * m);
-            gkv = mk<C>(w0 * gkv.x + wl * lv.x + wr * rv.x, w0 * gkv.y + wl * lv.y + wr * rv.y);
+    // ---- real-space update (pixels t = 2m and 2m+1 of x[m])
+    uint32_t mwd[MW];
+    const uint32_t* Mrow = maskw + (((size_t)n * N + z) * TT + tau) * MW;
+    sfor<0, MW>([&](auto iv) CPRA_INLINE { mwd[decltype(iv)::value] = Mrow[decltype(iv)::value]; });
+    Coupling cp{};
+    if (couple) cp = coup[n];
+    const T* gl = gin + ((size_t)cp.left * N + z) * N;
+    const T* gr = gin + ((size_t)cp.right * N + z) * N;
+    const T wl = (T)cp.wl, w0 = (T)cp.w0, wr = (T)cp.wr;
+    sfor<0, SPT>([&](auto jv) CPRA_INLINE {
+      constexpr int jj = decltype(jv)::value;
+      sfor<0, F1>([&](auto mv) CPRA_INLINE {
+        constexpr int m1 = decltype(mv)::value;
+        const int m = tau + TT * jj + F2 * m1;
+        const C gp = sp[jj][m1];                      // (g'[2m], g'[2m+1])
+        C out = gp;
+        if (mode != 0) {
+          constexpr int b0 = (jj * F1 + m1) * 2;
+          const bool s0 = (mwd[b0 >> 5] >> (b0 & 31)) & 1u;
+          const bool s1 = (mwd[(b0 + 1) >> 5] >> ((b0 + 1) & 31)) & 1u;
+          const bool g0 = s0 && (!positivity || gp.x >= (T)0);
+          const bool g1 = s1 && (!positivity || gp.y >= (T)0);
+          if (mode == 2) {
+            out = mk<C>(g0 ? gp.x : (T)0, g1 ? gp.y : (T)0);
+          } else {
+            C gkv = gk[jj][m1];
+            if (couple) {
+              C lv, rv;
+              if (cp.mirror_left) lv = mk<C>(gl[(N - 2 * m) & (N - 1)], gl[N - 1 - 2 * m]);
+              else lv = *reinterpret_cast<const C*>(gl + 2 * m);
+              if (cp.mirror_right) rv = mk<C>(gr[(N - 2 * m) & (N - 1)], gr[N - 1 - 2 * m]);
+              else rv = *reinterpret_cast<const C*>(gr + 2 * m);
+              gkv = mk<C>(w0 * gkv.x + wl * lv.x + wr * rv.x, w0 * gkv.y + wl * lv.y + wr * rv.y);
+            }
+            out = mk<C>(g0 ? gp.x : gkv.x - beta * gp.x, g1 ? gp.y : gkv.y - beta * gp.y);
           }
-          out = mk<C>(g0 ? gp.x : gkv.x - beta * gp.x, g1 ? gp.y : gkv.y - beta * gp.y);
         }
-      }
-      *reinterpret_cast<C*>(gout + rowr + 2 * m) = out;
-      sp[jj][m1] = out;
+        *reinterpret_cast<C*>(gout + rowr + 2 * m) = out;
+        sp[jj][m1] = out;
+      });
     });
-  });
+    __syncthreads();   // everyone has read the C2R exchange
   }
-  }   // mode != 3
   // ---- R2C step 1: for owned m2, F1-point DFT over m1, twiddle e^{-2 pi i m2 k1 / L}
-  __syncthreads();   // everyone has read the C2R exchange
   sfor<0, SPT>([&](auto jv) CPRA_INLINE {
     constexpr int jj = decltype(jv)::value;
     const int m2 = tau + TT * jj;
     dft<F1, -1>(sp[jj]);
-    const C* tp = tw + TL::RR2C + m2 * F1;            // e^{-2 pi i m2 k1 / L}
+    const C* tq = tw + TL::RR2C + m2 * F1;
     sfor<0, F1 / 2>([&](auto kv) CPRA_INLINE {
       constexpr int k1 = 2 * decltype(kv)::value;
       C t0w, t1w;
-      load_pair(tp + k1, t0w, t1w);
+      load_pair(tq + k1, t0w, t1w);
       C v0 = sp[jj][k1];
       if (k1 != 0) v0 = cmul(v0, t0w);
       L0[m2 * LS + k1] = v0;
@@ -945,38 +974,37 @@ __global__ void __launch_bounds__(RowCfg<N>::F1 / 2 * RowCfg<N>::RPB)
     });
   });
   __syncthreads();
-  // ---- R2C step 2: for owned classes, F2-point DFT over m2 -> Z[k1 + F1 k2]
-  sfor<0, 2>([&](auto ss) CPRA_INLINE {
-    constexpr int s = decltype(ss)::value;
-    const int k1 = k1v[s];
-    sfor<0, F2>([&](auto mm) CPRA_INLINE {
-      constexpr int m2 = decltype(mm)::value;
-      x[s][m2] = L0[m2 * LS + k1];
-    });
-    dft<F2, -1>(x[s]);
+  // ---- R2C step 2: class tau, F2-point DFT over m2 -> Z[tau + F1 k2]
+  sfor<0, F2>([&](auto mm) CPRA_INLINE {
+    constexpr int m2 = decltype(mm)::value;
+    x[m2] = L0[m2 * LS + tau];
   });
-  // ---- post-processing to the packed half spectrum, store
-  sfor<0, 2>([&](auto ss) CPRA_INLINE {
-    constexpr int s = decltype(ss)::value;
-    const int k1 = k1v[s];
-    const C* tp = tw + TL::RPP + k1 * F2;             // W_N^{k1 + F1 k2}
+  dft<F2, -1>(x);
+  // ---- post-processing to the packed half spectrum:
+  //   Fe = (Z[k] + conj Z[L-k])/2, Fo = (Z[k] - conj Z[L-k])/(2i), S[k] = Fe + W_N^k Fo
+  {
+    C zp[F2];
+    sfor<0, F2>([&](auto kk) CPRA_INLINE {
+      constexpr int k2 = decltype(kk)::value;
+      const C other = partner_c<F1>(x[F2 - 1 - k2], plane_lane);
+      const C self0 = x[(F2 - k2) % F2];
+      zp[k2] = t0 ? self0 : other;
+    });
+    const C* tp = tw + TL::RPP + tau * F2;
     sfor<0, F2 / 2>([&](auto kk) CPRA_INLINE {
       C tpair[2];
       load_pair(tp + 2 * decltype(kk)::value, tpair[0], tpair[1]);
       sfor<0, 2>([&](auto hh) CPRA_INLINE {
         constexpr int k2 = 2 * decltype(kk)::value + decltype(hh)::value;
-        constexpr int pk_t0 = (s == 0) ? ((F2 - k2) % F2) : (F2 - 1 - k2);
-        const C Z = x[s][k2];
-        const C za = x[s][pk_t0], zb = x[1 - s][F2 - 1 - k2];
-        const C Zp = mk<C>(t0 ? za.x : zb.x, t0 ? za.y : zb.y);
-        const bool k0 = (s == 0 && k2 == 0) && t0;
+        const C Z = x[k2], Zp = zp[k2];
+        const bool k0 = (k2 == 0) && t0;
         const C Fe = mk<C>((T)0.5 * (Z.x + Zp.x), (T)0.5 * (Z.y - Zp.y));
         const C Fo = mk<C>((T)0.5 * (Z.y + Zp.y), (T)0.5 * (Zp.x - Z.x));
         const C o = cadd(Fe, cmul(Fo, tpair[decltype(hh)::value]));
-        P[rowc + k1 + F1 * k2] = k0 ? mk<C>(Z.x + Z.y, Z.x - Z.y) : o;
+        P[rowc + tau + F1 * k2] = k0 ? mk<C>(Z.x + Z.y, Z.x - Z.y) : o;
       });
     });
-  });
+  }
 }
 
 // ---------------------------------------------------------------- error reduce
