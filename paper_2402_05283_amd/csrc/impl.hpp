@@ -120,19 +120,29 @@ struct Impl {
                                       CG::TILES, 0);
     };
     if constexpr (CG::S == 2) {
-      if (errpart) launch(k_col_pair<N, T, AP, 0, true>, errpart);
-      else launch(k_col_pair<N, T, AP, 0, false>, nullptr);
+      if (couple) {
+        if (errpart) launch(k_col_pair<N, T, AP, 0, true, true>, errpart);
+        else launch(k_col_pair<N, T, AP, 0, false, true>, nullptr);
+      } else {
+        if (errpart) launch(k_col_pair<N, T, AP, 0, true, false>, errpart);
+        else launch(k_col_pair<N, T, AP, 0, false, false>, nullptr);
+      }
     } else {
-      if (errpart) launch(k_col<N, T, AP, 0, true>, errpart);
-      else launch(k_col<N, T, AP, 0, false>, nullptr);
+      if (couple) {
+        if (errpart) launch(k_col<N, T, AP, 0, true, true>, errpart);
+        else launch(k_col<N, T, AP, 0, false, true>, nullptr);
+      } else {
+        if (errpart) launch(k_col<N, T, AP, 0, true, false>, errpart);
+        else launch(k_col<N, T, AP, 0, false, false>, nullptr);
+      }
     }
     if (e1) (void)hipEventRecord(e1, pl->stream);
     T* gin = at<T>(pl, pl->cur ? pl->L.g1 : pl->L.g0);
     T* gout = couple ? at<T>(pl, pl->cur ? pl->L.g0 : pl->L.g1) : gin;
     dim3 gr(N / RG::RPB, nact), br(RG::T * RG::RPB);
-    k_row<N, T><<<gr, br, 0, pl->stream>>>(at<C>(pl, pl->L.Pmid), at<C>(pl, pl->L.P), gin, gout,
-                                          at<uint32_t>(pl, pl->L.maskw), at<C>(pl, pl->L.tw), al, cp, couple ? 1 : 0,
-                                          mode, (T)beta, pl->p.positivity);
+    auto row = couple ? k_row<N, T, true> : k_row<N, T, false>;
+    row<<<gr, br, 0, pl->stream>>>(at<C>(pl, pl->L.Pmid), at<C>(pl, pl->L.P), gin, gout, at<uint32_t>(pl, pl->L.maskw),
+                                   at<C>(pl, pl->L.tw), al, cp, couple ? 1 : 0, mode, (T)beta, pl->p.positivity);
     if (e2) (void)hipEventRecord(e2, pl->stream);
   }
   // row spectra P = F_t(g) of the listed angles from the iterate in buffer gbuf
@@ -145,8 +155,8 @@ struct Impl {
   }
   static void assemble(cpra_plan_t pl, void* vol) {
     stepd_run<N, T>(at<C>(pl, pl->L.P), at<int>(pl, pl->L.csr_ptr), at<int>(pl, pl->L.csr_ent),
-                    at<T>(pl, pl->L.cnt_inv), at<C>(pl, pl->L.plane), pl->L.zc, reinterpret_cast<T*>(vol),
-                    pl->stream);
+                    at<T>(pl, pl->L.cnt_inv), at<C>(pl, pl->L.tw), at<C>(pl, pl->L.plane), pl->L.zc,
+                    reinterpret_cast<T*>(vol), pl->stream);
   }
 };
 

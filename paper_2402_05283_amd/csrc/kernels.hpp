@@ -367,7 +367,7 @@ __device__ __forceinline__ void block_reduce_store(double v, double* out) {
 // MODE 0: iteration (read P, optionally coupled; FFT_z; error; modulus
 // projection; IFFT_z; write Pmid).  MODE 1: initial guess (generate the
 // Hermitian part of (-1)^(w+u) A e^{i phi} / N^2, IFFT_z, write Pmid).
-template <int N, typename T, typename AP, int MODE, bool ERR>
+template <int N, typename T, typename AP, int MODE, bool ERR, bool CPL = false>
 __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
     k_col(const cx<T>* __restrict__ P, cx<T>* __restrict__ Pmid, const AP* __restrict__ A2,
           const T* __restrict__ ampscale, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
         if constexpr (PREFETCH) amp[i] = AmpIO<AP>::raw(An + (size_t)(a + R1 * q + R2 * d) * H + j);
       });
     }
-    if (couple) {
+    if (CPL) {
       const Coupling cp = coup[n];
       const T wl = (T)cp.wl, w0 = (T)cp.w0, wr = (T)cp.wr;
       const C* Pl = P + (size_t)cp.left * plane;
@@ -584,7 +584,7 @@ __device__ __forceinline__ cx<T> xor_lane(cx<T> v, int mask) {
   return mk<cx<T>>(__shfl_xor(v.x, mask), __shfl_xor(v.y, mask));
 }
 
-template <int N, typename T, typename AP, int MODE, bool ERR>
+template <int N, typename T, typename AP, int MODE, bool ERR, bool CPL = false>
 __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((amdgpu_waves_per_eu(4)))
     k_col_pair(const cx<T>* __restrict__ P, cx<T>* __restrict__ Pmid, const AP* __restrict__ A2,
                const T* __restrict__ ampscale, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
@@ -627,7 +627,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
         amp[k] = AmpIO<AP>::raw(An + (size_t)(c + R2 * (k + R2 * sh)) * H + j);
       });
     }
-    if (couple) {
+    if (CPL) {
       const Coupling cp = coup[n];
       const T wl = (T)cp.wl, w0 = (T)cp.w0, wr = (T)cp.wr;
       const C* Pl = P + (size_t)cp.left * plane;
@@ -816,7 +816,7 @@ __device__ __forceinline__ C partner_c(C v, int partner_lane_idx) {
 // exchange, F1-point IDFT) -> g' in the space layout; real-space update with
 // the support bits and g; R2C back (F1-point DFT, twiddle, LDS exchange,
 // F2-point DFT, post-processing) -> P.
-template <int N, typename T>
+template <int N, typename T, bool CPL = false>
 __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((amdgpu_waves_per_eu(4)))
     k_row(const cx<T>* __restrict__ Pmid, cx<T>* __restrict__ P, const T* gin, T* gout,
           const uint32_t* __restrict__ maskw, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
@@ -864,16 +864,15 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
     // ---- load Pmid class tau, C2R pre-processing:
     //   X'[k] = (a + b) + i (a - b) e^{+2 pi i k/N},  a = T[k], b = conj T[L-k]
     // (k = 0: a, b = the packed real DC and Nyquist values)
-    sfor<0, F2>([&](auto kk) CPRA_INLINE {
-      constexpr int k2 = decltype(kk)::value;
-      x[k2] = Pmid[rowc + tau + F1 * k2];
-    });
+    // the partner T[L-k] of k = tau + F1 k2 is read straight from memory: class
+    // (F1 - tau) at index F2-1-k2, or for class 0 its own index (F2 - k2) mod F2
+    // (same cache lines as this wave's own loads)
+    const int pcls = (F1 - tau) & (F1 - 1);
     C pv[F2];
     sfor<0, F2>([&](auto kk) CPRA_INLINE {
       constexpr int k2 = decltype(kk)::value;
-      const C other = partner_c<F1>(x[F2 - 1 - k2], plane_lane);   // partner lane, index F2-1-k2
-      const C self0 = x[(F2 - k2) % F2];                            // class 0 pairs with itself
-      pv[k2] = t0 ? self0 : other;
+      x[k2] = Pmid[rowc + tau + F1 * k2];
+      pv[k2] = Pmid[rowc + pcls + F1 * (t0 ? (F2 - k2) % F2 : F2 - 1 - k2)];
     });
     const C* tp = tw + TL::RPP + tau * F2;             // W_N^{k1 + F1 k2}
     sfor<0, F2 / 2>([&](auto kk) CPRA_INLINE {
@@ -919,7 +918,7 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
     const uint32_t* Mrow = maskw + (((size_t)n * N + z) * TT + tau) * MW;
     sfor<0, MW>([&](auto iv) CPRA_INLINE { mwd[decltype(iv)::value] = Mrow[decltype(iv)::value]; });
     Coupling cp{};
-    if (couple) cp = coup[n];
+    if constexpr (CPL) cp = coup[n];
     const T* gl = gin + ((size_t)cp.left * N + z) * N;
     const T* gr = gin + ((size_t)cp.right * N + z) * N;
     const T wl = (T)cp.wl, w0 = (T)cp.w0, wr = (T)cp.wr;
@@ -940,7 +939,7 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
             out = mk<C>(g0 ? gp.x : (T)0, g1 ? gp.y : (T)0);
           } else {
             C gkv = gk[jj][m1];
-            if (couple) {
+            if constexpr (CPL) {
               C lv, rv;
               if (cp.mirror_left) lv = mk<C>(gl[(N - 2 * m) & (N - 1)], gl[N - 1 - 2 * m]);
               else lv = *reinterpret_cast<const C*>(gl + 2 * m);
@@ -983,20 +982,16 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
   // ---- post-processing to the packed half spectrum:
   //   Fe = (Z[k] + conj Z[L-k])/2, Fo = (Z[k] - conj Z[L-k])/(2i), S[k] = Fe + W_N^k Fo
   {
-    C zp[F2];
-    sfor<0, F2>([&](auto kk) CPRA_INLINE {
-      constexpr int k2 = decltype(kk)::value;
-      const C other = partner_c<F1>(x[F2 - 1 - k2], plane_lane);
-      const C self0 = x[(F2 - k2) % F2];
-      zp[k2] = t0 ? self0 : other;
-    });
     const C* tp = tw + TL::RPP + tau * F2;
     sfor<0, F2 / 2>([&](auto kk) CPRA_INLINE {
       C tpair[2];
       load_pair(tp + 2 * decltype(kk)::value, tpair[0], tpair[1]);
       sfor<0, 2>([&](auto hh) CPRA_INLINE {
         constexpr int k2 = 2 * decltype(kk)::value + decltype(hh)::value;
-        const C Z = x[k2], Zp = zp[k2];
+        const C other = partner_c<F1>(x[F2 - 1 - k2], plane_lane);   // Z[L-k] from the partner lane
+        const C self0 = x[(F2 - k2) % F2];                            // class 0 pairs with itself
+        const C Z = x[k2];
+        const C Zp = t0 ? self0 : other;
         const bool k0 = (k2 == 0) && t0;
         const C Fe = mk<C>((T)0.5 * (Z.x + Zp.x), (T)0.5 * (Z.y - Zp.y));
         const C Fo = mk<C>((T)0.5 * (Z.y + Zp.y), (T)0.5 * (Zp.x - Z.x));

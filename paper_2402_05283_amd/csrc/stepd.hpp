@@ -14,6 +14,15 @@
 
 namespace cpra {
 
+// decomposition of the length-N inverse transforms of step D: N = R1 * R2,
+// R1 threads per row / column with R2 values each (R2 a multiple of R1)
+template <int N> struct StepdCfg;
+template <> struct StepdCfg<64> { static constexpr int R1 = 8, R2 = 8; };
+template <> struct StepdCfg<128> { static constexpr int R1 = 8, R2 = 16; };
+template <> struct StepdCfg<256> { static constexpr int R1 = 16, R2 = 16; };
+template <> struct StepdCfg<512> { static constexpr int R1 = 16, R2 = 32; };
+template <> struct StepdCfg<1024> { static constexpr int R1 = 32, R2 = 32; };
+
 template <int N, typename T>
 __device__ __forceinline__ cx<T> spectrum_at(const cx<T>* Prow, int u) {
   constexpr int H = N / 2;
@@ -27,11 +36,12 @@ __device__ __forceinline__ cx<T> spectrum_at(const cx<T>* Prow, int u) {
 // Rows: gather Q_z[ky][:] and inverse transform along kx.
 // Block: RB rows x R1 threads; grid: (N / RB, zc).
 template <int N, typename T, int RB>
-__global__ void __launch_bounds__(ColCfg<N>::R1* RB)
+__global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
     k_stepd_rows(const cx<T>* __restrict__ P, const int* __restrict__ ptr, const int* __restrict__ ent,
-                 const T* __restrict__ cnt_inv, cx<T>* __restrict__ plane, int z0) {
+                 const T* __restrict__ cnt_inv, const cx<T>* __restrict__ tw, cx<T>* __restrict__ plane, int z0) {
   using C = cx<T>;
-  constexpr int R1 = ColCfg<N>::R1, R2 = ColCfg<N>::R2, Q = R2 / R1, H = N / 2;
+  constexpr int R1 = StepdCfg<N>::R1, R2 = StepdCfg<N>::R2, Q = R2 / R1, H = N / 2;
+  static_assert(R1 * R2 == N && Q >= 1 && R2 % R1 == 0, "step D decomposition");
   constexpr int LS = R1 + 1;
   __shared__ C lds[RB * R2 * LS];
   const int a = threadIdx.x % R1;
@@ -60,14 +70,8 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* RB)
   }
   // inverse four-step along kx = a + R1 b -> x = c + R2 d
   dft<R2, +1>(v);
-  C tw1;
 #pragma unroll
-  for (int c = 0; c < R2; ++c) {
-    double s, co;
-    sincospi(2.0 * (double)((a * c) % N) / (double)N, &s, &co);
-    tw1 = mk<C>((T)co, (T)s);
-    L0[c * LS + a] = (c == 0 || a == 0) ? v[c] : cmul(v[c], tw1);
-  }
+  for (int c = 0; c < R2; ++c) L0[c * LS + a] = (c == 0 || a == 0) ? v[c] : cmulc(v[c], tw[(a * c) & (N - 1)]);
   __syncthreads();
   C* out = plane + ((size_t)zi * N + ky) * N;
 #pragma unroll
@@ -85,10 +89,10 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* RB)
 // Columns: inverse transform along ky, real part / N^2 -> volume [z][y][x].
 // Block: C columns x R1 threads; grid: (N / C, zc).
 template <int N, typename T, int CC>
-__global__ void __launch_bounds__(ColCfg<N>::R1* CC)
-    k_stepd_cols(const cx<T>* __restrict__ plane, T* __restrict__ vol, int z0) {
+__global__ void __launch_bounds__(StepdCfg<N>::R1* CC)
+    k_stepd_cols(const cx<T>* __restrict__ plane, const cx<T>* __restrict__ tw, T* __restrict__ vol, int z0) {
   using C = cx<T>;
-  constexpr int R1 = ColCfg<N>::R1, R2 = ColCfg<N>::R2, Q = R2 / R1;
+  constexpr int R1 = StepdCfg<N>::R1, R2 = StepdCfg<N>::R2, Q = R2 / R1;
   constexpr int LSTRIDE = R1 * CC + 1;
   __shared__ C lds[R2 * LSTRIDE];
   const int col = threadIdx.x % CC;
@@ -101,12 +105,8 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* CC)
   for (int b = 0; b < R2; ++b) v[b] = in[(size_t)(a + R1 * b) * N + x];
   dft<R2, +1>(v);
 #pragma unroll
-  for (int c = 0; c < R2; ++c) {
-    double s, co;
-    sincospi(2.0 * (double)((a * c) % N) / (double)N, &s, &co);
-    C t = mk<C>((T)co, (T)s);
-    lds[c * LSTRIDE + a * CC + col] = (c == 0 || a == 0) ? v[c] : cmul(v[c], t);
-  }
+  for (int c = 0; c < R2; ++c)
+    lds[c * LSTRIDE + a * CC + col] = (c == 0 || a == 0) ? v[c] : cmulc(v[c], tw[(a * c) & (N - 1)]);
   __syncthreads();
   const T norm = (T)1 / ((T)N * (T)N);
   T* out = vol + (size_t)(z0 + zi) * N * N;
@@ -122,16 +122,17 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* CC)
   }
 }
 
+// tw: W_N^j, j < N (the first N entries of the plan's twiddle table)
 template <int N, typename T>
-void stepd_run(const cx<T>* P, const int* ptr, const int* ent, const T* cnt_inv, cx<T>* plane, int zc, T* vol,
-               hipStream_t st) {
-  constexpr int R1 = ColCfg<N>::R1;
+void stepd_run(const cx<T>* P, const int* ptr, const int* ent, const T* cnt_inv, const cx<T>* tw, cx<T>* plane,
+               int zc, T* vol, hipStream_t st) {
+  constexpr int R1 = StepdCfg<N>::R1;
   constexpr int RB = (256 / R1) < N ? (256 / R1) : N;
   constexpr int CC = (256 / R1) < N ? (256 / R1) : N;
   for (int z0 = 0; z0 < N; z0 += zc) {
     const int nz = (N - z0) < zc ? (N - z0) : zc;
-    k_stepd_rows<N, T, RB><<<dim3(N / RB, nz), R1 * RB, 0, st>>>(P, ptr, ent, cnt_inv, plane, z0);
-    k_stepd_cols<N, T, CC><<<dim3(N / CC, nz), R1 * CC, 0, st>>>(plane, vol, z0);
+    k_stepd_rows<N, T, RB><<<dim3(N / RB, nz), R1 * RB, 0, st>>>(P, ptr, ent, cnt_inv, tw, plane, z0);
+    k_stepd_cols<N, T, CC><<<dim3(N / CC, nz), R1 * CC, 0, st>>>(plane, tw, vol, z0);
   }
 }
 

@@ -214,6 +214,28 @@ def test_step_d_larger_sizes(torch):
         assert rel_l2(vol, ref) <= 1e-10
 
 
+@pytest.mark.parametrize("real", [F32, F64])
+@pytest.mark.parametrize("N,Np", [(512, 5), (1024, 3)])
+def test_step_d_sampled_voxels(torch, N, Np, real):
+    """Step D at N = 512 and 1024 in the benchmark's launch configuration, checked at sampled
+    voxels that the oracle evaluates one by one from the definition."""
+    from oracle import stepd as D
+    scan = make_scan(1, N=N, Np=Np)
+    banner(f"step D sampled N={N} Np={Np} real={real}")
+    plan, obj, _ = run_gpu(scan, [(1, HIO, 0.9)], real=real, n_ei=1)
+    vol = plan.assemble_volume()
+    o, _ = run_oracle(scan, [(1, HIO, 0.9)], n_ei=1)
+    rng = np.random.default_rng(N)
+    pts = np.concatenate([rng.integers(N // 4, 3 * N // 4, size=(24, 3)), rng.integers(0, N, size=(8, 3)),
+                          np.array([[N // 2] * 3, [0, 0, 0], [N - 1, N // 2, 3]])])
+    idx = torch.from_numpy(pts).long().cuda()
+    got = vol[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+    ref = D.volume_at(o.g, scan["theta"], pts)
+    scale = np.abs(ref).max()
+    tol = 1e-4 if real == F32 else 1e-10
+    assert np.abs(got - ref).max() <= tol * scale
+
+
 def test_deterministic_and_homogeneous(torch):
     """Same inputs give bitwise-equal results; scaling I by 4 scales every iterate by exactly 2."""
     scan = make_scan(1, Np=6)

@@ -27,3 +27,16 @@ def test_single_slice_is_a_back_projection_smear():
     vol = D.assemble_volume(po, [0.0])
     # only the kx = 0 plane is filled: the volume is PO[z][y]/N along every x
     assert np.abs(vol - po[0][:, :, None] / N).max() <= 1e-13
+
+
+def test_volume_at_matches_literal_volume():
+    """The sampled-voxel evaluation agrees with the full N^3 form at every voxel asked for."""
+    N = 16
+    rng = np.random.default_rng(2)
+    po = rng.uniform(size=(5, N, N))
+    theta = np.pi * np.arange(5) / 5
+    vol = D.assemble_volume(po, theta)
+    pts = np.stack([rng.integers(0, N, 3) for _ in range(12)] + [np.array([N // 2] * 3)])
+    got = D.volume_at(po, theta, pts)
+    ref = vol[pts[:, 0], pts[:, 1], pts[:, 2]]
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(vol).max()
