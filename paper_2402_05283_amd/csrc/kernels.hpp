@@ -35,7 +35,7 @@ template <int N> struct ColCfg;
 template <> struct ColCfg<64> { static constexpr int R1 = 8, R2 = 8, C = 16, S = 1; };
 template <> struct ColCfg<128> { static constexpr int R1 = 8, R2 = 16, C = 16, S = 1; };
 template <> struct ColCfg<256> { static constexpr int R1 = 16, R2 = 16, C = 16, S = 1; };
-template <> struct ColCfg<512> { static constexpr int R1 = 32, R2 = 16, C = 16, S = 2; };
+template <> struct ColCfg<512> { static constexpr int R1 = 32, R2 = 16, C = 8, S = 2; };
 template <> struct ColCfg<1024> { static constexpr int R1 = 32, R2 = 32, C = 8, S = 1; };
 
 // Row half-spectrum transform of length L = N/2 = F1 * F2 (F1: frequency
@@ -74,6 +74,37 @@ template <int N> struct ColGeom {
   static_assert(R1 * R2 == N && (N / 2) % C == 0, "column decomposition");
   static_assert(S == 1 ? (R2 % R1 == 0) : (S == 2 && R1 / 2 == R2), "step-2 ownership");
 };
+
+// Storage of an angle's N x N/2 complex planes (P, Pmid) and of its amplitude
+// pairs: chunks of CB packed columns, each chunk stored [z][CB] contiguously,
+// so that a column-pass tile is one contiguous run of N*CB values (or, when
+// the column pass takes half a chunk per workgroup, runs of CB/2) and a row
+// pass block of rows reads CB-wide runs of consecutive rows.
+#ifndef CPRA_PIX512
+#define CPRA_PIX512 16
+#endif
+template <int N> struct PixCfg { static constexpr int CB = ColCfg<N>::C; };
+template <> struct PixCfg<512> { static constexpr int CB = CPRA_PIX512; };
+template <int N> __host__ __device__ __forceinline__ size_t pix(int z, int j) {
+  constexpr int CB = PixCfg<N>::CB;
+  return ((size_t)(j / CB) * N + z) * CB + (j % CB);
+}
+
+// First packed column of column-pass workgroup bx.  With CB = C one tile is
+// one chunk.  With CB = 2C, the two halves of a chunk go to workgroups bx and
+// bx + 8: the dispatcher deals consecutive workgroups round-robin to the 8
+// XCDs, so both halves land on one XCD (one L2) and close together in time,
+// and each 128-byte line of the chunk is fetched from HBM once.
+template <int N> __device__ __forceinline__ int col_tile_start(int bx) {
+  constexpr int C = ColCfg<N>::C, CB = PixCfg<N>::CB;
+  if constexpr (CB == C) {
+    return bx * C;
+  } else {
+    static_assert(CB == 2 * C && ((N / 2) / CB) % 8 == 0, "half-chunk tiles");
+    const int g = bx >> 4, r = bx & 15;
+    return (g * 8 + (r & 7)) * CB + (r >> 3) * C;
+  }
+}
 
 // Space position (t index) of support bit b of thread tau in a row; -1 past the last bit.
 template <int N> __host__ __device__ inline int mask_bit_t(int tau, int b) {
@@ -277,16 +308,16 @@ __global__ void __launch_bounds__(256) k_prep_encode(const float* __restrict__ I
       double a, b;
       if (j == 0) { a = ampd(w, 0); b = ampd(w, H); }
       else { a = ampd(w, j); b = ampd(wm, N - j); }
-      An[(size_t)w * H + j] = make_double2(a, b);
+      An[pix<N>(w, j)] = make_double2(a, b);
     } else {
       float a, b;
       if (j == 0) { a = ampf(w, 0); b = ampf(w, H); }
       else { a = ampf(w, j); b = ampf(wm, N - j); }
       if constexpr (std::is_same<AP, __half2>::value) {
         const float inv = 1.f / (float)ampscale[n];    // power of two: exact
-        An[(size_t)w * H + j] = __floats2half2_rn(a >= 0.f ? a * inv : -1.f, b >= 0.f ? b * inv : -1.f);
+        An[pix<N>(w, j)] = __floats2half2_rn(a >= 0.f ? a * inv : -1.f, b >= 0.f ? b * inv : -1.f);
       } else {
-        An[(size_t)w * H + j] = make_float2(a, b);
+        An[pix<N>(w, j)] = make_float2(a, b);
       }
     }
   }
@@ -385,6 +416,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
   const int tile = blockIdx.x;
   const int ai = blockIdx.y;
   const int n = alist[ai];
+  static_assert(PixCfg<N>::CB == CC, "one chunk per tile");
   const int j0 = tile * CC;
   const int j = j0 + col;
   const size_t plane = (size_t)N * H;
@@ -399,7 +431,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
     const C* Pn = P + (size_t)n * plane;
     sfor<0, R2>([&](auto bv) CPRA_INLINE {
       constexpr int b = decltype(bv)::value;
-      v[b] = Pn[(size_t)(a + R1 * b) * H + j];
+      v[b] = Pn[pix<N>(a + R1 * b, j)];
     });
     // amplitude pairs of the values this thread will hold after the forward
     // transform (w = a + R1 q + R2 d), fetched now so both HBM streams overlap
@@ -409,7 +441,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
       sfor<0, R2>([&](auto iv) CPRA_INLINE {
         constexpr int i = decltype(iv)::value;
         constexpr int q = i / R1, d = i % R1;
-        if constexpr (PREFETCH) amp[i] = AmpIO<AP>::raw(An + (size_t)(a + R1 * q + R2 * d) * H + j);
+        if constexpr (PREFETCH) amp[i] = AmpIO<AP>::raw(An + pix<N>(a + R1 * q + R2 * d, j));
       });
     }
     if (CPL) {
@@ -423,8 +455,8 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
       const T sr = (cp.mirror_right && j != 0) ? (T)-1 : (T)1;
       sfor<0, R2>([&](auto bv) CPRA_INLINE {
         constexpr int b = decltype(bv)::value;
-        const C l = Pl[(size_t)(a + R1 * b) * H + j];
-        const C r = Pr[(size_t)(a + R1 * b) * H + j];
+        const C l = Pl[pix<N>(a + R1 * b, j)];
+        const C r = Pr[pix<N>(a + R1 * b, j)];
         v[b] = mk<C>(w0 * v[b].x + wl * l.x + wr * r.x, w0 * v[b].y + (wl * sl) * l.y + (wr * sr) * r.y);
       });
     }
@@ -461,7 +493,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
         const int w = a + R1 * q + R2 * d;
         typename AmpIO<AP>::pair_t raw;
         if constexpr (PREFETCH) raw = amp[i];
-        else raw = AmpIO<AP>::raw(An + (size_t)w * H + j);
+        else raw = AmpIO<AP>::raw(An + pix<N>(w, j));
         const auto pa = AmpIO<AP>::decode(raw, as);
         g[i] = Proj<T>::template two<ERR>(g[i], (T)pa.x, (T)pa.y, ((w + j) & 1) != 0, scale, err, 1.0);
       });
@@ -483,15 +515,15 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
         constexpr int q = i / R1, d = i % R1;
         const int w = a + R1 * q + R2 * d;
         if (j != 0) {
-          const auto pa = AmpIO<AP>::load(An + (size_t)w * H + j, as);
+          const auto pa = AmpIO<AP>::load(An + pix<N>(w, j), as);
           g[i] = Proj<T>::template two<ERR>(g[i], (T)pa.x, (T)pa.y, ((w + j) & 1) != 0, scale, err, 1.0);
         } else {
           const int wm = (N - w) & (N - 1);
           const C Z = g[i], Zm = zl[wm];
           const C Ga = mk<C>((T)0.5 * (Z.x + Zm.x), (T)0.5 * (Z.y - Zm.y));
           const C Gb = mk<C>((T)0.5 * (Z.y + Zm.y), (T)0.5 * (Zm.x - Z.x));
-          const auto p0 = AmpIO<AP>::load(An + (size_t)w * H, as);     // (A(w,0), A(w,N/2))
-          const auto pm = AmpIO<AP>::load(An + (size_t)wm * H, as);    // (A(-w,0), A(-w,N/2))
+          const auto p0 = AmpIO<AP>::load(An + pix<N>(w, 0), as);     // (A(w,0), A(w,N/2))
+          const auto pm = AmpIO<AP>::load(An + pix<N>(wm, 0), as);    // (A(-w,0), A(-w,N/2))
           // each of w, -w is visited once per column: half weight on the paired error terms
           const C Pa = Proj<T>::template two<ERR>(Ga, (T)p0.x, (T)pm.x, (w & 1) != 0, scale, err, 0.5);
           const C Pb = Proj<T>::template two<ERR>(Gb, (T)p0.y, (T)pm.y, ((w + H) & 1) != 0, scale, err, 0.5);
@@ -515,14 +547,14 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
       const int wm = (N - w) & (N - 1);
       C out;
       if (j != 0) {
-        const auto pa = AmpIO<AP>::load(An + (size_t)w * H + j, as);
+        const auto pa = AmpIO<AP>::load(An + pix<N>(w, j), as);
         const T a1 = pa.x > (T)0 ? (T)pa.x : (T)0, a2 = pa.y > (T)0 ? (T)pa.y : (T)0;
         const C e1 = phase(w, j), e2 = conj(phase(wm, N - j));
         const T sg = ((w + j) & 1) ? -scale : scale;
         out = mk<C>(sg * (a1 * e1.x + a2 * e2.x), sg * (a1 * e1.y + a2 * e2.y));
       } else {
-        const auto p0 = AmpIO<AP>::load(An + (size_t)w * H, as);
-        const auto pm = AmpIO<AP>::load(An + (size_t)wm * H, as);
+        const auto p0 = AmpIO<AP>::load(An + pix<N>(w, 0), as);
+        const auto pm = AmpIO<AP>::load(An + pix<N>(wm, 0), as);
         const T a0 = p0.x > 0 ? (T)p0.x : (T)0, am0 = pm.x > 0 ? (T)pm.x : (T)0;
         const T aH = p0.y > 0 ? (T)p0.y : (T)0, amH = pm.y > 0 ? (T)pm.y : (T)0;
         const C e1 = phase(w, 0), e2 = conj(phase(wm, 0));
@@ -565,7 +597,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
     C* Mn = Pmid + (size_t)n * plane;
     sfor<0, R2>([&](auto bv) CPRA_INLINE {
       constexpr int b = decltype(bv)::value;
-      Mn[(size_t)(a + R1 * b) * H + j] = v[b];
+      Mn[pix<N>(a + R1 * b, j)] = v[b];
     });
   }
   if constexpr (MODE == 0 && ERR) {
@@ -579,9 +611,10 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
 // parity, a W_R1^{s k'} twiddle and a radix-2 butterfly with its partner
 // lane (a ^ 1, i.e. lane ^ C).  It then holds G[w] for w = c + R2 (k' + R2 s).
 // The inverse mirrors it.  Same modes and outputs as k_col.
-template <typename T>
-__device__ __forceinline__ cx<T> xor_lane(cx<T> v, int mask) {
-  return mk<cx<T>>(__shfl_xor(v.x, mask), __shfl_xor(v.y, mask));
+// value of lane ^ PM (the step-2 partner)
+template <int PM, typename T>
+__device__ __forceinline__ cx<T> pair_lane(cx<T> v) {
+  return mk<cx<T>>(__shfl_xor(v.x, PM), __shfl_xor(v.y, PM));
 }
 
 template <int N, typename T, typename AP, int MODE, bool ERR, bool CPL = false>
@@ -598,13 +631,17 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
   static_assert(Gm::S == 2, "paired kernel");
   __shared__ C lds[R2 * LSTRIDE];
   __shared__ C zl[(MODE == 0) ? N : 1];
+  // lane = a * CC + col: the lanes of one row of a tile are neighbours, and the
+  // step-2 partner (a ^ 1) is lane ^ CC
+  constexpr int PM = CC;
   const int col = threadIdx.x % CC;
   const int a = threadIdx.x / CC;          // row residue in step 1
-  const int c = a >> 1, sh = a & 1;        // step 2: owned c and half
+  const int sh = a & 1;
+  const int c = a >> 1;                    // step 2: owned c and half sh
   const int tile = blockIdx.x;
   const int ai = blockIdx.y;
   const int n = alist[ai];
-  const int j0 = tile * CC;
+  const int j0 = col_tile_start<N>(tile);
   const int j = j0 + col;
   const size_t plane = (size_t)N * H;
   const T scale = (T)0.5 / ((T)N * (T)N);
@@ -618,13 +655,13 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
     const C* Pn = P + (size_t)n * plane;
     sfor<0, R2>([&](auto bv) CPRA_INLINE {
       constexpr int b = decltype(bv)::value;
-      v[b] = Pn[(size_t)(a + R1 * b) * H + j];
+      v[b] = Pn[pix<N>(a + R1 * b, j)];
     });
     typename AmpIO<AP>::pair_t amp[R2];
     if (j0 != 0) {
       sfor<0, R2>([&](auto kv) CPRA_INLINE {
         constexpr int k = decltype(kv)::value;
-        amp[k] = AmpIO<AP>::raw(An + (size_t)(c + R2 * (k + R2 * sh)) * H + j);
+        amp[k] = AmpIO<AP>::raw(An + pix<N>(c + R2 * (k + R2 * sh), j));
       });
     }
     if (CPL) {
@@ -636,8 +673,8 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
       const T sr = (cp.mirror_right && j != 0) ? (T)-1 : (T)1;
       sfor<0, R2>([&](auto bv) CPRA_INLINE {
         constexpr int b = decltype(bv)::value;
-        const C l = Pl[(size_t)(a + R1 * b) * H + j];
-        const C r = Pr[(size_t)(a + R1 * b) * H + j];
+        const C l = Pl[pix<N>(a + R1 * b, j)];
+        const C r = Pr[pix<N>(a + R1 * b, j)];
         v[b] = mk<C>(w0 * v[b].x + wl * l.x + wr * r.x, w0 * v[b].y + (wl * sl) * l.y + (wr * sr) * r.y);
       });
     }
@@ -662,19 +699,20 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
       g[k] = lds[c * LSTRIDE + (sh + 2 * k) * CC + col];
     });
     dft<R2, -1>(g);
+    const T sgn = sh ? (T)-1 : (T)1;
     sfor<0, R2>([&](auto kv) CPRA_INLINE {
       constexpr int k = decltype(kv)::value;
       const C t = sh ? twc<-1, k, R1>(g[k]) : g[k];
-      const C o = xor_lane<T>(t, CC);
-      g[k] = sh ? csub(o, t) : cadd(t, o);
+      const C o = pair_lane<PM, T>(t);
+      g[k] = mk<C>(o.x + sgn * t.x, o.y + sgn * t.y);    // sh = 0: t + o; sh = 1: o - t
     });
     // modulus projection
     if (j0 != 0) {
+      const bool neg = ((c + j) & 1) != 0;   // (-1)^(w + j), w = c + R2 (k + R2 sh), R2 even
       sfor<0, R2>([&](auto kv) CPRA_INLINE {
         constexpr int k = decltype(kv)::value;
-        const int w = c + R2 * (k + R2 * sh);
         const auto pa = AmpIO<AP>::decode(amp[k], as);
-        g[k] = Proj<T>::template two<ERR>(g[k], (T)pa.x, (T)pa.y, ((w + j) & 1) != 0, scale, err, 1.0);
+        g[k] = Proj<T>::template two<ERR>(g[k], (T)pa.x, (T)pa.y, neg, scale, err, 1.0);
       });
     } else {
       __syncthreads();
@@ -689,15 +727,15 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
         constexpr int k = decltype(kv)::value;
         const int w = c + R2 * (k + R2 * sh);
         if (j != 0) {
-          const auto pa = AmpIO<AP>::load(An + (size_t)w * H + j, as);
+          const auto pa = AmpIO<AP>::load(An + pix<N>(w, j), as);
           g[k] = Proj<T>::template two<ERR>(g[k], (T)pa.x, (T)pa.y, ((w + j) & 1) != 0, scale, err, 1.0);
         } else {
           const int wm = (N - w) & (N - 1);
           const C Z = g[k], Zm = zl[wm];
           const C Ga = mk<C>((T)0.5 * (Z.x + Zm.x), (T)0.5 * (Z.y - Zm.y));
           const C Gb = mk<C>((T)0.5 * (Z.y + Zm.y), (T)0.5 * (Zm.x - Z.x));
-          const auto p0 = AmpIO<AP>::load(An + (size_t)w * H, as);
-          const auto pm = AmpIO<AP>::load(An + (size_t)wm * H, as);
+          const auto p0 = AmpIO<AP>::load(An + pix<N>(w, 0), as);
+          const auto pm = AmpIO<AP>::load(An + pix<N>(wm, 0), as);
           const C Pa = Proj<T>::template two<ERR>(Ga, (T)p0.x, (T)pm.x, (w & 1) != 0, scale, err, 0.5);
           const C Pb = Proj<T>::template two<ERR>(Gb, (T)p0.y, (T)pm.y, ((w + H) & 1) != 0, scale, err, 0.5);
           g[k] = mk<C>(Pa.x - Pb.y, Pa.y + Pb.x);
@@ -718,14 +756,14 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
       const int wm = (N - w) & (N - 1);
       C out;
       if (j != 0) {
-        const auto pa = AmpIO<AP>::load(An + (size_t)w * H + j, as);
+        const auto pa = AmpIO<AP>::load(An + pix<N>(w, j), as);
         const T a1 = pa.x > (T)0 ? (T)pa.x : (T)0, a2 = pa.y > (T)0 ? (T)pa.y : (T)0;
         const C e1 = phase(w, j), e2 = conj(phase(wm, N - j));
         const T sg = ((w + j) & 1) ? -scale : scale;
         out = mk<C>(sg * (a1 * e1.x + a2 * e2.x), sg * (a1 * e1.y + a2 * e2.y));
       } else {
-        const auto p0 = AmpIO<AP>::load(An + (size_t)w * H, as);
-        const auto pm = AmpIO<AP>::load(An + (size_t)wm * H, as);
+        const auto p0 = AmpIO<AP>::load(An + pix<N>(w, 0), as);
+        const auto pm = AmpIO<AP>::load(An + pix<N>(wm, 0), as);
         const T a0 = p0.x > 0 ? (T)p0.x : (T)0, am0 = pm.x > 0 ? (T)pm.x : (T)0;
         const T aH = p0.y > 0 ? (T)p0.y : (T)0, amH = pm.y > 0 ? (T)pm.y : (T)0;
         const C e1 = phase(w, 0), e2 = conj(phase(wm, 0));
@@ -741,12 +779,15 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
 
   // inverse: radix-2 butterfly across the lane pair, W_R1^{-sh k'}, R2-point IDFT over k'
   if constexpr (MODE == 0) __syncthreads();   // all forward reads of lds are done
-  sfor<0, R2>([&](auto kv) CPRA_INLINE {
-    constexpr int k = decltype(kv)::value;
-    const C o = xor_lane<T>(g[k], CC);
-    const C u = sh ? csub(o, g[k]) : cadd(g[k], o);
-    g[k] = sh ? twc<+1, k, R1>(u) : u;
-  });
+  {
+    const T sgn = sh ? (T)-1 : (T)1;
+    sfor<0, R2>([&](auto kv) CPRA_INLINE {
+      constexpr int k = decltype(kv)::value;
+      const C o = pair_lane<PM, T>(g[k]);
+      const C u = mk<C>(o.x + sgn * g[k].x, o.y + sgn * g[k].y);
+      g[k] = sh ? twc<+1, k, R1>(u) : u;
+    });
+  }
   dft<R2, +1>(g);   // g[a'] = Y'[c][sh + 2 a']
   {
     const C* ti = tw + TL::COLI + c * R1 + sh * R2;   // conj W_N^{(sh + 2a') c}
@@ -769,7 +810,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
     C* Mn = Pmid + (size_t)n * plane;
     sfor<0, R2>([&](auto bv) CPRA_INLINE {
       constexpr int b = decltype(bv)::value;
-      Mn[(size_t)(a + R1 * b) * H + j] = v[b];
+      Mn[pix<N>(a + R1 * b, j)] = v[b];
     });
   }
   if constexpr (MODE == 0 && ERR) {
@@ -833,7 +874,7 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
   const int n = alist[blockIdx.y];
   const int z = blockIdx.x * RPB + r;
   C* L0 = lds + r * Gm::RSTRIDE;
-  const size_t rowc = ((size_t)n * N + z) * H;     // complex row base
+  const size_t pbase = (size_t)n * N * H;           // the angle's complex planes
   const size_t rowr = ((size_t)n * N + z) * N;     // real row base
   const bool t0 = (tau == 0);
   const int plane_lane = (threadIdx.x & ~(TT - 1)) + ((TT - tau) & (TT - 1));   // partner, for __shfl
@@ -871,8 +912,8 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
     C pv[F2];
     sfor<0, F2>([&](auto kk) CPRA_INLINE {
       constexpr int k2 = decltype(kk)::value;
-      x[k2] = Pmid[rowc + tau + F1 * k2];
-      pv[k2] = Pmid[rowc + pcls + F1 * (t0 ? (F2 - k2) % F2 : F2 - 1 - k2)];
+      x[k2] = Pmid[pbase + pix<N>(z, tau + F1 * k2)];
+      pv[k2] = Pmid[pbase + pix<N>(z, pcls + F1 * (t0 ? (F2 - k2) % F2 : F2 - 1 - k2))];
     });
     const C* tp = tw + TL::RPP + tau * F2;             // W_N^{k1 + F1 k2}
     sfor<0, F2 / 2>([&](auto kk) CPRA_INLINE {
@@ -996,7 +1037,7 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
         const C Fe = mk<C>((T)0.5 * (Z.x + Zp.x), (T)0.5 * (Z.y - Zp.y));
         const C Fo = mk<C>((T)0.5 * (Z.y + Zp.y), (T)0.5 * (Zp.x - Z.x));
         const C o = cadd(Fe, cmul(Fo, tpair[decltype(hh)::value]));
-        P[rowc + tau + F1 * k2] = k0 ? mk<C>(Z.x + Z.y, Z.x - Z.y) : o;
+        P[pbase + pix<N>(z, tau + F1 * k2)] = k0 ? mk<C>(Z.x + Z.y, Z.x - Z.y) : o;
       });
     });
   }

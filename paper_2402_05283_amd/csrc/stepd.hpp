@@ -23,14 +23,15 @@ template <> struct StepdCfg<256> { static constexpr int R1 = 16, R2 = 16; };
 template <> struct StepdCfg<512> { static constexpr int R1 = 16, R2 = 32; };
 template <> struct StepdCfg<1024> { static constexpr int R1 = 32, R2 = 32; };
 
+// S[z][u] of an angle from its packed half spectrum Pn (layout pix<N>)
 template <int N, typename T>
-__device__ __forceinline__ cx<T> spectrum_at(const cx<T>* Prow, int u) {
+__device__ __forceinline__ cx<T> spectrum_at(const cx<T>* Pn, int z, int u) {
   constexpr int H = N / 2;
   using C = cx<T>;
-  if (u == 0) return mk<C>(Prow[0].x, (T)0);
-  if (u == H) return mk<C>(Prow[0].y, (T)0);
-  if (u < H) return Prow[u];
-  return conj(Prow[N - u]);
+  if (u == 0) return mk<C>(Pn[pix<N>(z, 0)].x, (T)0);
+  if (u == H) return mk<C>(Pn[pix<N>(z, 0)].y, (T)0);
+  if (u < H) return Pn[pix<N>(z, u)];
+  return conj(Pn[pix<N>(z, N - u)]);
 }
 
 // Rows: gather Q_z[ky][:] and inverse transform along kx.
@@ -60,7 +61,7 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
     for (int e = ptr[cell]; e < e1; ++e) {
       const int code = ent[e];
       const int n = code / N, u = code % N;
-      C s = spectrum_at<N, T>(P + ((size_t)n * N + z) * H, u);
+      C s = spectrum_at<N, T>(P + (size_t)n * N * H, z, u);
       if (u & 1) { s.x = -s.x; s.y = -s.y; }
       acc = cadd(acc, s);
     }
