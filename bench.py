@@ -29,6 +29,9 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 ROOT = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(ROOT, "paper_2402_05283_amd", "csrc")
+TRAFFIC_MD = os.path.join(ROOT, "profiles", "traffic_col_row_n512_np360.md")
+COPY_BYTES = 1 << 30           # plain device copy used to calibrate the HBM byte counters
 
 N, NP, ITERS, N_EI, BETA = 512, 360, 200, 10, 0.9
 
@@ -84,6 +87,126 @@ print(json.dumps({{"submit_s": t1 - t0, "iter_s": t2 - t1}}))
                       f"{r['iter_s']:.1f} s iterate + {r['submit_s']:.1f} s submit"}
 
 
+def kernel_source_hash():
+    """SHA-256 over the sources that define the column and row passes and their launches."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("cx.hpp", "kernels.hpp", "impl.hpp"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def load_traffic():
+    """HBM bytes per launch from the committed counter summary, or None when the kernel
+    sources have changed since those counters were taken."""
+    try:
+        with open(TRAFFIC_MD) as fh:
+            for line in fh:
+                if line.startswith("traffic-json: "):
+                    d = json.loads(line[len("traffic-json: "):])
+                    return d if d.get("source_sha256") == kernel_source_hash() else None
+    except OSError:
+        pass
+    return None
+
+
+def _pmc_rows(d):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return rows
+
+
+def summarize_pmc(fetch_dir, write_dir, cmd):
+    """Markdown summary of a FETCH_SIZE run and a WRITE_SIZE run of `bench.py --calibrate-copy`:
+    per-dispatch HBM bytes of the column and row passes, scaled by what the same counters
+    read for the plain 1 GiB device copy."""
+    import re
+
+    def per_kernel(rows, counter):
+        acc = {}
+        for r in rows:
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"]
+            v = float(r["Counter_Value"]) * 1024.0      # counters are KiB per dispatch
+            if "copyBuffer" in name and v > COPY_BYTES / 2:
+                key = "copy"
+            else:
+                if re.search(r"cpra::k_row<512, float\b", name):
+                    key = "k_row"
+                elif re.search(r"cpra::k_col(_pair)?<512, float, [^,]+, 2u>, 0,", name):
+                    key = "k_col"                          # iteration column pass (not the initial guess)
+                else:
+                    continue
+            acc.setdefault(key, []).append(v)
+        return acc
+
+    fetch = per_kernel(_pmc_rows(fetch_dir), "FETCH_SIZE")
+    write = per_kernel(_pmc_rows(write_dir), "WRITE_SIZE")
+    if "copy" not in fetch or "copy" not in write:
+        raise SystemExit("the 1 GiB calibration copy is missing from the counter runs")
+    ff = COPY_BYTES / (sum(fetch["copy"]) / len(fetch["copy"]))
+    fw = COPY_BYTES / (sum(write["copy"]) / len(write["copy"]))
+    col_b, row_b = algorithmic_bytes(N, NP, N_EI)
+    model = {"k_col": col_b, "k_row": row_b}
+    out = {"source_sha256": kernel_source_hash(), "fetch_factor": ff, "write_factor": fw}
+    lines = ["# HBM traffic of the column and row passes: N=512, Np=360 cell scan", "",
+             "Commands (repo root, one MI355X; one counter per run):", "",
+             f"    {cmd.format(counter='FETCH_SIZE', out='pmc_fetch')}",
+             f"    {cmd.format(counter='WRITE_SIZE', out='pmc_write')}",
+             f"    python3 bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write", "",
+             f"Calibration: a plain device copy of {COPY_BYTES >> 20} MiB reads "
+             f"{sum(fetch['copy']) / len(fetch['copy']) / 2**20:.1f} MiB on FETCH_SIZE and "
+             f"{sum(write['copy']) / len(write['copy']) / 2**20:.1f} MiB on WRITE_SIZE, so fetches are scaled "
+             f"by {ff:.3f} and writes by {fw:.3f}.", "",
+             "| Kernel (per 360-angle launch, all iteration launches) | Launches | Fetch (GB) | Write (GB) | "
+             "HBM total (GB) | Algorithmic (GB) | Ratio |", "|---|---|---|---|---|---|---|"]
+    for k in ("k_col", "k_row"):
+        fb = ff * sum(fetch[k]) / len(fetch[k])
+        wb = fw * sum(write[k]) / len(write[k])
+        out[k] = {"fetch_bytes": fb, "write_bytes": wb, "traffic_bytes": fb + wb, "launches": len(fetch[k])}
+        lines.append(f"| {k} | {len(fetch[k])} | {fb / 1e9:.3f} | {wb / 1e9:.3f} | {(fb + wb) / 1e9:.3f} | "
+                     f"{model[k] / 1e9:.3f} | {(fb + wb) / model[k]:.3f} |")
+    lines += ["", "The line below is read by bench.py, which reports `traffic` only while the kernel "
+              "sources hash to the same value.", "", "traffic-json: " + json.dumps(out)]
+    return "\n".join(lines) + "\n"
+
+
+def summarize_trace(trace_dir, bench_json, cmd):
+    """Markdown summary of a `rocprofv3 --kernel-trace --stats` run of bench.py, beside the
+    launch durations that bench.py measured itself with HIP events in the same run."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel_stats.csv under {trace_dir}")
+    with open(files[0]) as fh:
+        rows = list(csv.DictReader(fh))
+    with open(bench_json) as fh:
+        b = json.loads([l for l in fh if l.startswith("{")][-1])
+    r = b["roofline"]
+    ev = {r["kernel"]: r["avg_launch_ms"], r["other"]["kernel"]: r["other"]["avg_launch_ms"]}
+    lines = ["# Kernel-trace summary: N=512, Np=360 cell scan, whole reconstruction per step", "",
+             "Command (repo root, one MI355X):", "", f"    {cmd}", "",
+             f"Each step: plan set-up, submit of 360 angles (prep + initial objects), {b['config']['iterations']} "
+             f"HIO iterations (coupling every {b['config']['n_ei']}), step D into a 512^3 volume.  "
+             f"bench.py in the same run: value {b['value']:.0f} pattern-iterations/s, {b['ms_per_step']:.1f} ms "
+             f"per step; HIP-event mean launch time k_col {ev.get('k_col', 0) * 1e3:.1f} us, "
+             f"k_row {ev.get('k_row', 0) * 1e3:.1f} us.", "",
+             "| Kernel | Calls | Total ms | Avg us | % |", "|---|---|---|---|---|"]
+    for x in rows:
+        lines.append(f"| `{x['Name'][:110]}` | {x['Calls']} | {float(x['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(x['AverageNs']) / 1e3:.1f} | {float(x['Percentage']):.1f} |")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,7 +215,23 @@ def main():
     ap.add_argument("--amp16", action="store_true", help="FP16 amplitude storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters", type=int, default=ITERS)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (the byte-counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the traffic summary of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
+                    help="print the kernel-trace summary of a rocprofv3 --stats run and exit")
     args = ap.parse_args()
+    if args.summarize_trace:
+        cmd = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace -o run "
+               "-- python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline > gpurun_out/trace_bench.json")
+        print(summarize_trace(*args.summarize_trace, cmd), end="")
+        return
+    if args.summarize_pmc:
+        cmd = ("timeout -s KILL 120 rocprofv3 --pmc {counter} --output-format csv -d gpurun_out/{out} -o run "
+               "-- python3 bench.py --steps 1 --warmup 0 --iters 20 --no-cpu-baseline --calibrate-copy")
+        print(summarize_pmc(*args.summarize_pmc, cmd), end="")
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU (multi-GPU sharding is a design note only); "
               "use --gpus 1", file=sys.stderr)
@@ -116,6 +255,14 @@ def main():
     vol = torch.empty((N, N, N), dtype=torch.float32, device=dev)
     amp = cp.AMP_F16 if args.amp16 else cp.AMP_F32
     stream = torch.cuda.current_stream(dev)
+
+    if args.calibrate_copy:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     col_ms = row_ms = 0.0
     col_n = row_n = 0
@@ -155,8 +302,10 @@ def main():
     col_gbs = col_b / (col_avg * 1e-3) / 1e9
     row_gbs = row_b / (row_avg * 1e-3) / 1e9
     dom = ("k_col", col_avg, col_gbs, col_b) if col_avg >= row_avg else ("k_row", row_avg, row_gbs, row_b)
+    tr = load_traffic() if not args.amp16 else None
+    traffic = round(tr[dom[0]]["traffic_bytes"]) if tr else None
     roofline = {"bound": "hbm", "achieved": round(dom[2], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dom[2] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom[0],
+                "frac": round(dom[2] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom[0],
                 "avg_launch_ms": round(dom[1], 5), "bytes_per_launch": int(dom[3]),
                 "other": {"kernel": "k_row" if dom[0] == "k_col" else "k_col",
                           "avg_launch_ms": round(row_avg if dom[0] == "k_col" else col_avg, 5),
