@@ -116,6 +116,23 @@ cpra_status cpra_submit_angles(cpra_plan_t plan, int32_t first, int32_t count,
 cpra_status cpra_iterate(cpra_plan_t plan, int32_t n_iter, int32_t algo, double beta, double* err_out);
 
 /*
+ * Several independent scans at once (the data-parallel dimension of steps B
+ * and C over scans rather than angles): `count` distinct plans, possibly of
+ * different N and Np, each advance n_iter iterations with the same algo and
+ * beta.  Each plan's episode phase follows its own k, exactly as
+ * cpra_iterate would.  The iterations are issued interleaved, iteration by
+ * iteration and plan by plan, each on its own plan's stream, so plans on
+ * different streams overlap on the device.  Results are those of calling
+ * cpra_iterate on each plan alone.  No error history is returned (use
+ * cpra_iterate for that).  Checks every plan first: NULL array, NULL or
+ * repeated plans, a poisoned plan, or a plan with no angle return
+ * ERR_ARG / ERR_STATE and no plan advances.  A device error poisons the
+ * plan it occurred in and returns ERR_DEVICE; the others stay usable.
+ * Asynchronous.
+ */
+cpra_status cpra_iterate_batch(cpra_plan_t* plans, int32_t count, int32_t n_iter, int32_t algo, double beta);
+
+/*
  * Current real-space iterate of every angle, Np x N x N [n][z][t] centred,
  * float (F32 plans) or double (F64 plans), host or device.  At an episode
  * end this is the episode's estimate.  Host copies synchronise the stream.

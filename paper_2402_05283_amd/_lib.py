@@ -28,6 +28,7 @@ EXPORTED = [
     "cpra_workspace_size", "cpra_plan_create", "cpra_submit_angles", "cpra_iterate", "cpra_read_objects",
     "cpra_assemble_volume", "cpra_destroy", "cpra_last_error", "cpra_iteration_count", "cpra_slice_cells",
     "cpra_coupling_table", "cpra_set_kernel_timing", "cpra_kernel_timing", "cpra_load_objects",
+    "cpra_iterate_batch",
 ]
 
 
@@ -73,6 +74,7 @@ def load():
     lib.cpra_read_objects.argtypes = [c.c_void_p, c.c_void_p, c.c_int32]
     lib.cpra_assemble_volume.argtypes = [c.c_void_p, c.c_void_p]
     lib.cpra_destroy.argtypes = [c.c_void_p]
+    lib.cpra_iterate_batch.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_int32, c.c_double]
     lib.cpra_last_error.argtypes = [c.c_void_p]
     lib.cpra_last_error.restype = c.c_char_p
     lib.cpra_iteration_count.argtypes = [c.c_void_p, P(c.c_int64)]
@@ -92,6 +94,15 @@ def _check(st, plan=None):
     if st != CPRA_OK:
         msg = load().cpra_last_error(plan)
         raise CpraError(st, msg.decode() if msg else "")
+
+
+def iterate_batch(plans, n_iter, algo=HIO, beta=0.9):
+    """cpra_iterate_batch over a list of Plan objects (each on its own stream, ideally)."""
+    handles = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
+    st = load().cpra_iterate_batch(handles, len(plans), int(n_iter), int(algo), float(beta))
+    if st != CPRA_OK:
+        msgs = [load().cpra_last_error(p.handle) for p in plans] + [load().cpra_last_error(None)]
+        raise CpraError(st, "; ".join(m.decode() for m in msgs if m))
 
 
 def make_params(N, Np, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=WRAP_MIRROR, positivity=True,
@@ -162,6 +173,22 @@ class Plan:
         _check(st, None)
         self.handle = handle
 
+    def _enter(self):
+        """Order the plan's stream after the caller's current stream (tensors handed in were
+        produced there)."""
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _leave(self, *tensors):
+        """Order the caller's current stream after the plan's stream, and keep tensors the
+        library touched alive for the plan's stream."""
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+            for t in tensors:
+                t.record_stream(self.stream)
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
@@ -182,6 +209,7 @@ class Plan:
             if I.dtype != torch.float32 or S.dtype != torch.uint8 or not I.is_cuda or not S.is_cuda:
                 raise TypeError("device inputs must be CUDA float32 intensity and uint8 support")
             count = I.shape[0]
+            self._enter()       # the library reads I and S on its stream and synchronises before returning
             st = load().cpra_submit_angles(self.handle, first, count, ctypes.c_void_p(I.data_ptr()),
                                            ctypes.c_void_p(S.data_ptr()), PTR_DEVICE)
         _check(st, self.handle)
@@ -197,7 +225,9 @@ class Plan:
         torch = self.torch
         if out is None:
             out = torch.empty((self.Np, self.N, self.N), dtype=self.dtype, device=self.device)
+        self._enter()
         _check(load().cpra_read_objects(self.handle, ctypes.c_void_p(out.data_ptr()), PTR_DEVICE), self.handle)
+        self._leave(out)
         return out
 
     def load_objects(self, objects):
@@ -212,6 +242,7 @@ class Plan:
             a = objects.contiguous()
             if a.dtype != self.dtype or tuple(a.shape) != (self.Np, self.N, self.N) or not a.is_cuda:
                 raise TypeError("objects must be a CUDA tensor of shape (Np, N, N) in the plan's precision")
+            self._enter()       # synchronises before returning
             st = load().cpra_load_objects(self.handle, ctypes.c_void_p(a.data_ptr()), PTR_DEVICE)
         _check(st, self.handle)
 
@@ -219,7 +250,9 @@ class Plan:
         torch = self.torch
         if out is None:
             out = torch.empty((self.N, self.N, self.N), dtype=self.dtype, device=self.device)
+        self._enter()
         _check(load().cpra_assemble_volume(self.handle, ctypes.c_void_p(out.data_ptr())), self.handle)
+        self._leave(out)
         return out
 
     def set_kernel_timing(self, enable=True):

@@ -295,6 +295,55 @@ cpra_status cpra_submit_angles(cpra_plan_t pl, int32_t first, int32_t count, con
   return CPRA_OK;
 }
 
+// one iteration of one plan with no error history: episode bookkeeping, then the two passes
+static cpra_status step_once(cpra_plan_t pl, const Ops& ops, int32_t algo, double beta) {
+  const bool boundary = (pl->k % pl->p.n_ei) == 0;
+  if (boundary && pl->present != pl->landed) {
+    pl->present = pl->landed;
+    pl->tables_dirty = true;
+  }
+  if (pl->tables_dirty) {
+    cpra_status st = upload_tables(pl);
+    if (st != CPRA_OK) return st;
+  }
+  const int nact = (int)pl->alist_h.size();
+  const bool estimate = ((pl->k + 1) % pl->p.n_ei) == 0;
+  const int mode = estimate ? 2 : (algo == CPRA_HIO ? 1 : 2);
+  ops.step(pl, nact, boundary, mode, beta, nullptr);
+  LAUNCHCHK(pl);
+  if (boundary) pl->cur ^= 1;
+  pl->k += 1;
+  return CPRA_OK;
+}
+
+cpra_status cpra_iterate_batch(cpra_plan_t* plans, int32_t count, int32_t n_iter, int32_t algo, double beta) {
+  if (!plans) return fail(nullptr, CPRA_ERR_ARG, "plans is NULL");
+  if (count < 0) return fail(nullptr, CPRA_ERR_ARG, "count < 0");
+  for (int i = 0; i < count; ++i) {
+    cpra_plan_t pl = plans[i];
+    if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plans[%d] is NULL", i);
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == pl) return fail(pl, CPRA_ERR_ARG, "plan %d repeated at %d", j, i);
+    if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
+    if (n_iter < 0) return fail(pl, CPRA_ERR_ARG, "n_iter < 0");
+    if (algo != CPRA_HIO && algo != CPRA_ER) return fail(pl, CPRA_ERR_ARG, "bad algo");
+    if (!std::isfinite(beta)) return fail(pl, CPRA_ERR_ARG, "beta must be finite");
+    bool any = false;
+    for (int n = 0; n < pl->p.Np; ++n) any = any || pl->landed[n];
+    if (!any) return fail(pl, CPRA_ERR_STATE, "no angle has been submitted");
+  }
+  std::vector<Ops> ops(count);
+  for (int i = 0; i < count; ++i) ops[i] = ops_of(plans[i]->p);
+  cpra_status worst = CPRA_OK;
+  for (int it = 0; it < n_iter; ++it)
+    for (int i = 0; i < count; ++i) {
+      if (plans[i]->poisoned) continue;
+      const cpra_status st = step_once(plans[i], ops[i], algo, beta);
+      if (st != CPRA_OK) worst = st;
+    }
+  return worst;
+}
+
 cpra_status cpra_iterate(cpra_plan_t pl, int32_t n_iter, int32_t algo, double beta, double* err_out) {
   if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
   if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");

@@ -92,3 +92,15 @@ def test_single_angle_coupling_table():
     p = cp.make_params(64, 1, alpha=(0.25, 0.5, 0.25))
     left, right, w, mirror = cp.coupling_table(p)
     assert left[0] == 0 and right[0] == 0 and mirror[0].tolist() == [1, 1]
+
+
+def test_iterate_batch_argument_checks_need_no_device():
+    """Argument errors of cpra_iterate_batch are reported before any device call."""
+    import ctypes
+    lib = cp.load()
+    assert lib.cpra_iterate_batch(None, 1, 1, 0, 0.9) == -1
+    one_null = (ctypes.c_void_p * 1)(None)
+    assert lib.cpra_iterate_batch(one_null, 1, 1, 0, 0.9) == -1
+    assert b"NULL" in lib.cpra_last_error(None)
+    assert lib.cpra_iterate_batch(one_null, -1, 1, 0, 0.9) == -1
+    assert lib.cpra_iterate_batch(one_null, 0, 1, 0, 0.9) == 0      # nothing to do

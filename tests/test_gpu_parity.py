@@ -275,6 +275,47 @@ def test_fp16_amplitudes_error_is_small(torch):
         assert r16 <= lim16
 
 
+def test_iterate_batch_matches_alone(torch):
+    """cpra_iterate_batch: three scans of different N and Np, each on its own stream and at a
+    different episode phase, advance together and end bit-identical to the same scans iterated
+    alone (same kernels, same order of arithmetic)."""
+    import paper_2402_05283_amd as cp
+    scans = [make_scan(1, N=64, Np=16), make_scan(1, N=128, Np=6), make_scan(1, N=256, Np=3)]
+
+    def make(scan, stream):
+        p = cp.Plan(scan["N"], scan["Np"], theta=scan["theta"], n_ei=5, seed=scan["phase_seed"], stream=stream)
+        p.submit(0, torch.from_numpy(scan["I"]).cuda(), torch.from_numpy(scan["support"]).cuda())
+        p.iterate(1 + scan["Np"] % 4, cp.HIO, 0.9)          # k = 1, 3, 4: different episode phases
+        return p
+
+    banner("iterate_batch alone")
+    alone = []
+    for sc in scans:
+        p = make(sc, None)
+        p.iterate(12, cp.HIO, 0.9)
+        p.iterate(3, cp.ER, 0.0)
+        torch.cuda.synchronize()
+        alone.append((p.k, p.objects().cpu().numpy()))
+    banner("iterate_batch mixed")
+    streams = [torch.cuda.Stream() for _ in scans]
+    plans = [make(sc, s) for sc, s in zip(scans, streams)]
+    cp.iterate_batch(plans, 12, cp.HIO, 0.9)
+    cp.iterate_batch(plans, 3, cp.ER, 0.0)
+    torch.cuda.synchronize()
+    for p, (k, ref) in zip(plans, alone):
+        assert p.k == k
+        assert np.array_equal(p.objects().cpu().numpy(), ref)
+    # argument errors leave every plan where it was
+    with pytest.raises(cp.CpraError) as e:
+        cp.iterate_batch([plans[0], plans[1], plans[0]], 2)
+    assert e.value.status == -1
+    empty = cp.Plan(64, 4, n_ei=5)
+    with pytest.raises(cp.CpraError) as e:
+        cp.iterate_batch([plans[0], empty], 2)
+    assert e.value.status == -4
+    assert [p.k for p in plans] == [k for k, _ in alone]
+
+
 def test_api_errors(torch):
     import paper_2402_05283_amd as cp
     scan = make_scan(1, Np=4)
