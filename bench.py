@@ -12,7 +12,10 @@ Also reported:
     pass on the plan's stream, algorithmic bytes per launch / mean duration);
   * cpu_baseline: the FP64 oracle on a bounded sample (8 angles x 3
     iterations, single thread) on this machine's host;
-  * per-step latency percentiles (submit to volume).
+  * last-frame-to-volume latency under the serving loop: 8 concurrent scans
+    of the same shape whose frames land at 20 frames/s each, reconstructed on
+    partial angle sets as they land (about 20 s of wall time; --serve-scans 0
+    skips it, --serve-rounds R repeats it for R x 8 samples).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -207,6 +210,37 @@ def summarize_trace(trace_dir, bench_json, cmd):
     return "\n".join(lines) + "\n"
 
 
+def serving_latency(cp, torch, scan, I, S, args):
+    """Last-frame-to-volume latency under the serving loop: `serve_scans` scans of the same shape
+    (N=512, Np=360; the bench scan's frames, a different phase seed each) open 0.25 s apart in each
+    round, rounds one scan-duration apart; frames land at serve_fps per scan in angle order; each
+    landed frame earns 10 iterations (one episode), the last one 50 more, then step D."""
+    from paper_2402_05283_amd import serve
+    T = NP / args.serve_fps
+    jobs = []
+    for r in range(args.serve_rounds):
+        for i in range(args.serve_scans):
+            jobs.append(serve.Job(r * T + 0.25 * i, N, NP, (lambda n: (I[n:n + 1], S[n:n + 1])), args.serve_fps,
+                                  seed=scan["phase_seed"] + 1 + r * args.serve_scans + i))
+    srv = serve.Server(200 << 30, n_ei=N_EI, r_frame=N_EI, r_final=50, algo=cp.HIO, beta=BETA)
+    print(f"[bench] serving {len(jobs)} scans at {args.serve_fps} frames/s each "
+          f"(~{T * args.serve_rounds + 0.25 * args.serve_scans:.0f} s)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    done = serve.replay(srv, jobs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([d.latency_s for d in done]) * 1e3
+    work = sum(d.iters_done for d in done)
+    print(f"[bench] serving done in {wall:.1f} s; latency p50 {np.percentile(lat, 50):.1f} ms, "
+          f"max {lat.max():.1f} ms", file=sys.stderr, flush=True)
+    return {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
+            "max": round(float(lat.max()), 2), "samples": int(lat.size),
+            "what": f"last frame to volume ready: {args.serve_scans} concurrent N={N} Np={NP} scans per round, "
+                    f"{args.serve_rounds} round(s), {args.serve_fps:g} frames/s each, 10 HIO iterations per landed "
+                    f"frame (partial angle sets), 50 after the last, then step D",
+            "serving_wall_s": round(wall, 2), "scan_iterations": int(work)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +249,9 @@ def main():
     ap.add_argument("--amp16", action="store_true", help="FP16 amplitude storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters", type=int, default=ITERS)
+    ap.add_argument("--serve-scans", type=int, default=8, help="concurrent scans in the serving leg (0: skip)")
+    ap.add_argument("--serve-rounds", type=int, default=1, help="serving rounds (latency samples = scans x rounds)")
+    ap.add_argument("--serve-fps", type=float, default=20.0, help="frames per second per scan")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (the byte-counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -329,11 +366,14 @@ def main():
                    "N": N, "N_p": NP, "iterations": args.iters, "n_ei": N_EI},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 2),
                        "p99": round(float(np.percentile(lat, 99)) * 1e3, 2),
-                       "what": "submit-to-volume time of a whole scan handed over at once"},
+                       "what": "submit-to-volume time of a whole scan handed over at once (serving leg skipped)"},
         "iteration_only": {"ms_per_iteration": round(iter_ms, 4),
                            "pattern_iterations_per_s": round(NP / (iter_ms * 1e-3), 1)},
         "roofline": roofline,
     }
+    if args.serve_scans > 0:
+        out["latency_ms"] = serving_latency(cp, torch, scan, I, S, args)
+        out["latency_ms"]["whole_scan_p50"] = round(float(np.percentile(lat, 50)) * 1e3, 2)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scan)

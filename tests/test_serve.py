@@ -1,0 +1,132 @@
+"""Serving loop logic on the CPU: admission by footprint, the logical schedule and latency
+bookkeeping, with stand-in plans that record what the server asks of them (no GPU)."""
+import contextlib
+
+import pytest
+
+from paper_2402_05283_amd import serve
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class Done:
+    def query(self):
+        return True
+
+
+class FakePlan:
+    def __init__(self, scan, log):
+        self.scan, self.log, self.k = scan, log, 0
+        self.stream = None
+
+    def submit(self, n, I, S):
+        self.log.append((self.scan.sid, "submit", n, self.k))
+
+    def iterate(self, n):
+        self.k += n
+        self.log.append((self.scan.sid, "iterate", n, self.k))
+
+    def assemble_volume(self):
+        self.log.append((self.scan.sid, "volume", self.k))
+        return ("volume", self.scan.sid, self.k)
+
+    def record_event(self):
+        return Done()
+
+
+def make_server(budget, log, clock, **kw):
+    def batch(plans, n):
+        for p in plans:
+            p.iterate(n)
+    return serve.Server(budget, clock=clock, plan_factory=lambda s: FakePlan(s, log), batch_fn=batch,
+                        stream_ctx=lambda p: contextlib.nullcontext(), **kw)
+
+
+def run(server, clock, jobs, order_seed=0):
+    """Push frames per the jobs' schedules with a fake clock, stepping the server between."""
+    import random
+    rng = random.Random(order_seed)
+    scans = {}
+    events = []
+    for ji, (t0, N, Np, fps) in enumerate(jobs):
+        events.append((t0, "open", ji, None))
+        for n in range(Np):
+            events.append((t0 + n / fps, "frame", ji, n))
+    events.sort(key=lambda e: (e[0], e[1] != "open"))
+    for t, kind, ji, n in events:
+        clock.t = t
+        if kind == "open":
+            scans[ji] = server.open_scan(jobs[ji][1], jobs[ji][2], seed=ji)
+        else:
+            server.push_frame(scans[ji], n, None, None, t=t)
+        for _ in range(rng.randrange(0, 4)):      # a random amount of scheduling between arrivals
+            clock.t += 1e-3
+            server.step()
+    while server.busy():
+        clock.t += 1e-3
+        server.step()
+    return [scans[i] for i in range(len(jobs))]
+
+
+def ops_of(log, sid):
+    return [e[1:] for e in log if e[0] == sid]
+
+
+def test_schedule_is_logical_and_independent_of_the_mix():
+    clock = FakeClock()
+    alone_logs = []
+    jobs = [(0.0, 64, 5, 20.0), (0.01, 128, 3, 50.0), (0.02, 64, 4, 10.0)]
+    for ji, job in enumerate(jobs):
+        log = []
+        srv = make_server(1 << 40, log, clock, n_ei=5, r_frame=10, r_final=20)
+        clock.t = 0.0
+        run(srv, clock, [job], order_seed=ji)
+        alone_logs.append([e[1:] for e in log])
+    for seed in range(3):
+        log = []
+        srv = make_server(1 << 40, log, clock, n_ei=5, r_frame=10, r_final=20)
+        clock.t = 0.0
+        scans = run(srv, clock, jobs, order_seed=100 + seed)
+        for sid, sc in enumerate(scans):
+            assert ops_of(log, sc.sid) == alone_logs[sid]
+    # the schedule itself: frame j submitted at k = j * r_frame; r_final after the last frame
+    ops = alone_logs[0]
+    submits = [o for o in ops if o[0] == "submit"]
+    assert [o[2] for o in submits] == [0, 10, 20, 30, 40]
+    assert ops[-1] == ("volume", 5 * 10 + 20)
+    assert all(o[1] == 5 for o in ops if o[0] == "iterate")
+
+
+def test_admission_by_footprint_and_latency():
+    clock = FakeClock()
+    log = []
+    fp = serve.Server.footprint(64, 4)
+    srv = make_server(2 * fp + fp // 2, log, clock, n_ei=10, r_final=10)
+    jobs = [(0.0, 64, 4, 100.0), (0.0, 64, 4, 100.0), (0.0, 64, 4, 100.0)]
+    scans = run(srv, clock, jobs)
+    first_ops = {}
+    for i, e in enumerate(log):
+        first_ops.setdefault(e[0], i)
+    # the third scan only starts once one of the first two has finished and left
+    finish = min(max(i for i, e in enumerate(log) if e[0] == s) for s in (0, 1))
+    assert first_ops[2] > finish
+    for s in scans:
+        assert s.done and s.latency_s is not None and s.latency_s >= 0
+        assert s.volume == ("volume", s.sid, 4 * 10 + 10)
+    assert srv.used == 0
+
+
+def test_rejects_bad_schedules_and_oversized_scans():
+    with pytest.raises(ValueError):
+        serve.Server(1 << 30, n_ei=10, r_frame=15)
+    with pytest.raises(ValueError):
+        serve.Server(1 << 30, n_ei=10, r_final=5)
+    srv = serve.Server(1024)
+    with pytest.raises(ValueError):
+        srv.open_scan(64, 4)
