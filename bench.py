@@ -241,6 +241,147 @@ def serving_latency(cp, torch, scan, I, S, args):
             "serving_wall_s": round(wall, 2), "scan_iterations": int(work)}
 
 
+def plain_comparison(cp, torch, scan, I, S, args, cpra_iter_ms):
+    """CPRA against the plain per-angle method on the same GPU.
+
+    Plain method = the same 2D HIO with no carousel coupling (alpha = (0, 1, 0)): each angle is
+    reconstructed on its own.  Two measures of the result after 200 iterations:
+      * data fit: median over angles of E_F of the final episode estimates;
+      * 3D consistency: the fraction of angles whose estimate is nearer the true projection than
+        its twin (the point reflection, which fits the same intensities), and the relative L2
+        error of the step-D volume against the step-D volume of the true projections (after
+        choosing the better of the volume and its twin).
+    Three forms of the plain method are timed: (a) the project's kernels, all angles batched in
+    one plan, also run on until its median E_F reaches CPRA's (at most 1000 iterations); (b) a
+    straightforward unfused PyTorch version (torch.fft, i.e. rocFFT, over all angles at once,
+    elementwise projection and HIO update), from the same initial objects; (c) the project's
+    kernels at batch 1, one plan per angle, over a sample of angles."""
+    Np, N = scan["Np"], scan["N"]
+    th = scan["theta"]
+    A_nat = torch.fft.ifftshift(torch.sqrt(torch.clamp(I, min=0.0)), dim=(-2, -1))
+    den = (A_nat.double() ** 2).sum((-2, -1))
+    Sb = S.bool()
+    po = torch.from_numpy(scan["po"].astype(np.float32)).to(I.device)
+
+    def twin(x, dims):
+        for d in dims:
+            x = torch.roll(torch.flip(x, (d,)), 1, d)
+        return x
+
+    def quality(obj, vol_of):
+        err = torch.empty(Np, dtype=torch.float64, device=obj.device)
+        near_true = 0
+        for c0 in range(0, Np, 60):
+            o = obj[c0:c0 + 60]
+            G = torch.fft.fft2(o)
+            err[c0:c0 + 60] = torch.sqrt(((G.abs() - A_nat[c0:c0 + 60]) ** 2).double().sum((-2, -1))
+                                         / den[c0:c0 + 60])
+            p = po[c0:c0 + 60]
+            d0 = ((o - p) ** 2).sum((-2, -1))
+            d1 = ((o - twin(p, (-2, -1))) ** 2).sum((-2, -1))
+            near_true += int((d0 < d1).sum())
+        v = vol_of(obj)
+        ve = min(float(torch.linalg.norm(v - v_true)), float(torch.linalg.norm(twin(v, (0, 1, 2)) - v_true)))
+        frac = near_true / Np
+        return {"median_error": round(float(err.median()), 5),
+                "twin_consistency": round(max(frac, 1 - frac), 4),
+                "volume_error": round(ve / float(torch.linalg.norm(v_true)), 4)}
+
+    def plan(alpha, wrap, n=None):
+        th_ = th if n is None else th[n:n + 1]
+        p = cp.Plan(N, len(th_), theta=th_, alpha=alpha, wrap=wrap, n_ei=N_EI, seed=scan["phase_seed"])
+        if n is None:
+            p.submit(0, I, S)
+        else:
+            p.submit(0, I[n:n + 1], S[n:n + 1])
+        return p
+
+    vp = plan((0.2, 0.6, 0.2), cp.WRAP_MIRROR)
+    vp.iterate(N_EI, cp.HIO, BETA)                      # step D needs an episode end
+
+    def vol_of(obj):
+        vp.load_objects(obj)
+        return vp.assemble_volume()
+
+    v_true = vol_of(po).clone()
+    out = {}
+    pc = plan((0.2, 0.6, 0.2), cp.WRAP_MIRROR)
+    pc.iterate(ITERS, cp.HIO, BETA)
+    q_cpra = quality(pc.objects(), vol_of)
+    del pc
+    out["cpra"] = dict(iterations=ITERS, seconds=round(ITERS * cpra_iter_ms * 1e-3, 4), **q_cpra)
+
+    # (a) plain, project kernels, batched over angles
+    pp = plan((0.0, 1.0, 0.0), cp.WRAP_PLAIN)
+    w0 = pp.objects().clone()
+    k, hist, reached, elapsed, q200 = 0, [], None, 0.0, None
+    while k < 1000:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pp.iterate(50, cp.HIO, BETA)
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        k += 50
+        q = quality(pp.objects(), vol_of) if k == ITERS else None
+        if q is not None:
+            q200 = q
+        e = q["median_error"] if q else quality_error_only(torch, pp.objects(), A_nat, den)
+        hist.append((k, round(e, 5)))
+        if reached is None and e <= q_cpra["median_error"]:
+            reached = k
+        if reached is not None and k >= ITERS:
+            break
+    del pp
+    out["plain_batched"] = dict(at_200=q200, error_history=hist, iterations_to_cpra_error=reached,
+                                seconds_per_iteration=round(elapsed / k, 6),
+                                seconds_to_cpra_error=None if reached is None else round(elapsed / k * reached, 4))
+
+    # (b) plain, unfused torch.fft, from the same initial objects
+    g = w0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(ITERS):
+        G = torch.fft.fft2(g)
+        mag = G.abs()
+        # (|G| = 0 exactly does not occur on these scans; its zero-phase value is not special-cased)
+        Gp = G * (A_nat / torch.clamp(mag, min=1e-30))
+        gp = torch.fft.ifft2(Gp).real
+        gam = Sb & (gp >= 0)
+        if (it + 1) % N_EI == 0:
+            g = torch.where(gam, gp, torch.zeros_like(gp))
+        else:
+            g = torch.where(gam, gp, g - BETA * gp)
+    torch.cuda.synchronize()
+    t_torch = time.perf_counter() - t0
+    del G, Gp, gp, mag, gam
+    out["plain_torch_fft"] = dict(pattern_iterations_per_s=round(ITERS * Np / t_torch, 1), at_200=quality(g, vol_of),
+                                  what="torch.fft.fft2/ifft2 (rocFFT) over all angles at once, elementwise "
+                                       "projection and HIO in torch, complex64")
+    del g
+
+    # (c) plain, project kernels, batch 1 (one plan per angle) over a sample of angles
+    sample = list(range(0, Np, 10))
+    plans = [plan((0.0, 1.0, 0.0), cp.WRAP_PLAIN, n) for n in sample]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in plans:
+        p.iterate(ITERS, cp.HIO, BETA)
+    torch.cuda.synchronize()
+    t_b1 = time.perf_counter() - t0
+    del plans, vp
+    out["plain_batch1_loop"] = {"pattern_iterations_per_s": round(ITERS * len(sample) / t_b1, 1),
+                                "angles_timed": len(sample)}
+    return out
+
+
+def quality_error_only(torch, obj, A_nat, den):
+    err = []
+    for c0 in range(0, obj.shape[0], 60):
+        G = torch.fft.fft2(obj[c0:c0 + 60])
+        err.append(torch.sqrt(((G.abs() - A_nat[c0:c0 + 60]) ** 2).double().sum((-2, -1)) / den[c0:c0 + 60]))
+    return float(torch.cat(err).median())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +393,7 @@ def main():
     ap.add_argument("--serve-scans", type=int, default=8, help="concurrent scans in the serving leg (0: skip)")
     ap.add_argument("--serve-rounds", type=int, default=1, help="serving rounds (latency samples = scans x rounds)")
     ap.add_argument("--serve-fps", type=float, default=20.0, help="frames per second per scan")
+    ap.add_argument("--no-compare", action="store_true", help="skip the plain per-angle comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (the byte-counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -285,7 +427,7 @@ def main():
     torch.cuda.set_device(dev)
     print(f"[bench] generating the N={N} Np={NP} scan", file=sys.stderr, flush=True)
     t = time.time()
-    scan = make_scan(4)
+    scan = make_scan(4, keep_po=True)
     print(f"[bench] scan ready in {time.time() - t:.1f} s", file=sys.stderr, flush=True)
     I = torch.from_numpy(scan["I"]).to(dev)
     S = torch.from_numpy(scan["support"]).to(dev)
@@ -371,6 +513,9 @@ def main():
                            "pattern_iterations_per_s": round(NP / (iter_ms * 1e-3), 1)},
         "roofline": roofline,
     }
+    if not args.no_compare and args.iters == ITERS and not args.amp16:
+        print("[bench] plain per-angle comparison", file=sys.stderr, flush=True)
+        out["vs_plain_per_angle"] = plain_comparison(cp, torch, scan, I, S, args, iter_ms)
     if args.serve_scans > 0:
         out["latency_ms"] = serving_latency(cp, torch, scan, I, S, args)
         out["latency_ms"]["whole_scan_p50"] = round(float(np.percentile(lat, 50)) * 1e3, 2)
