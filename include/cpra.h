@@ -65,6 +65,10 @@ typedef struct {
   int32_t amp_type;      /* CPRA_AMP_F32, or CPRA_AMP_F16 (F32 plans only): sqrt(I) kept
                             as binary16 times a per-angle power-of-two scale            */
   uint64_t seed;         /* key of the counter-based SplitMix64 initial phases          */
+  int32_t n_guess;       /* N_r independent reconstructions of the scan held at once
+                            (step C's random guesses; 0 means 1).  Guess r of angle n is
+                            slot r * Np + n: its own iterate and random start (phase
+                            stream index r * Np + n), the angle's data shared.        */
 } cpra_params;
 
 /*
@@ -109,11 +113,56 @@ cpra_status cpra_submit_angles(cpra_plan_t plan, int32_t first, int32_t count,
  * HIO (algo CPRA_HIO): g <- g' on gamma, g - beta g' elsewhere;
  * ER (CPRA_ER): g <- g' on gamma, 0 elsewhere.  The last iteration of an
  * episode writes the estimate g' on gamma, 0 elsewhere.
- * err_out: NULL, or host n_iter x Np doubles receiving E_F (NaN for absent
- * angles); non-NULL synchronises the stream.  Otherwise asynchronous.
- * ERR_STATE if no angle is present.
+ * Every guess runs the same schedule on its own ring of slots.
+ * err_out: NULL, or host n_iter x (n_guess * Np) doubles receiving E_F per
+ * slot (NaN for absent angles); non-NULL synchronises the stream.  Otherwise
+ * asynchronous.  ERR_STATE if no angle is present.
  */
 cpra_status cpra_iterate(cpra_plan_t plan, int32_t n_iter, int32_t algo, double beta, double* err_out);
+
+/*
+ * Step A, pre-reconstruction: PO 1 (angle 0) of every guess runs n_iter
+ * iterations of plain 2D phase retrieval from its current object, with no
+ * coupling; the last iteration writes the estimate.  The other angles keep
+ * their random starts, which together make the first episode W_0.  Does
+ * not change k.  err_out: NULL, or host n_guess x n_iter doubles (E_F).
+ * ERR_STATE unless angle 0 has been submitted.  Synchronises only when
+ * err_out is non-NULL.
+ */
+cpra_status cpra_prereconstruct(cpra_plan_t plan, int32_t n_iter, int32_t algo, double beta, double* err_out);
+
+/*
+ * Step B in its consecutive form: n_episodes episodes, each taking the POs
+ * in order n = 0 .. Np-1.  PO n (of every guess at once) is re-initialised
+ * from Eq. 4 over its neighbours' most recent objects (n-1 from this
+ * episode, n+1 from the previous one, the ring wrapping with the t-mirror
+ * across the 180-degree seam under CPRA_WRAP_MIRROR), then runs n_ei
+ * iterations, the last writing its estimate.  Work is sequential over
+ * angles and parallel over guesses.  k advances by n_episodes * n_ei.
+ * err_out: NULL, or host n_episodes x n_guess x Np x n_ei doubles (E_F);
+ * non-NULL synchronises after every angle.  ERR_STATE unless every angle
+ * has been submitted and k mod n_ei == 0.
+ */
+cpra_status cpra_sweep(cpra_plan_t plan, int32_t n_episodes, int32_t algo, double beta, double* err_out);
+
+/*
+ * Step C, merge of the guesses.  Error of a guess: E = sqrt(sum_n sum_q
+ * (|F2 X_n| - A_n)^2 / sum_n sum_q A_n^2) over measured q, on its current
+ * objects X_n.  Keeps the n_best guesses of lowest E (ties in guess order);
+ * moves every kept PO's mass centre c = sum X r / sum X (r from the centre
+ * index N/2) to the origin by the cyclic integer shift floor(-c + 1/2) per
+ * axis; for every kept guess but the best, compares its shifted PO 1 with
+ * the best guess's shifted PO 1 and with its central inversion X(-r), and
+ * inverts all its POs if the inversion is nearer (squared distance, FP64);
+ * averages the kept guesses.  The result replaces guess 0's objects (slots
+ * 0 .. Np-1) and its row spectra, so cpra_read_objects (first Np planes)
+ * and cpra_assemble_volume (step D) use it; other guesses are unchanged.
+ * kept, inverted: NULL or host arrays of n_best entries receiving the kept
+ * guesses in rank order and whether each was inverted.  ERR_ARG unless
+ * 1 <= n_best <= n_guess; ERR_STATE unless every angle has been submitted
+ * and k mod n_ei == 0.  Synchronises the stream.
+ */
+cpra_status cpra_merge(cpra_plan_t plan, int32_t n_best, int32_t* kept, int32_t* inverted);
 
 /*
  * Several independent scans at once (the data-parallel dimension of steps B
@@ -133,16 +182,18 @@ cpra_status cpra_iterate(cpra_plan_t plan, int32_t n_iter, int32_t algo, double 
 cpra_status cpra_iterate_batch(cpra_plan_t* plans, int32_t count, int32_t n_iter, int32_t algo, double beta);
 
 /*
- * Current real-space iterate of every angle, Np x N x N [n][z][t] centred,
- * float (F32 plans) or double (F64 plans), host or device.  At an episode
- * end this is the episode's estimate.  Host copies synchronise the stream.
+ * Current real-space iterate of every slot, n_guess x Np x N x N [r][n][z][t]
+ * centred, float (F32 plans) or double (F64 plans), host or device.  At an
+ * episode end this is the episode's estimate.  Host copies synchronise the
+ * stream.
  */
 cpra_status cpra_read_objects(cpra_plan_t plan, void* out, int32_t ptr_kind);
 
 /*
  * Warm start: replace the current iterate of every submitted angle by
- * `objects` (Np x N x N [n][z][t] centred, float for F32 plans or double for
- * F64 plans; host or device; rows of angles not yet submitted are ignored)
+ * `objects` (n_guess x Np x N x N [r][n][z][t] centred, float for F32 plans
+ * or double for F64 plans; host or device; rows of angles not yet submitted
+ * are ignored)
  * and recompute the plan's internal row spectra from it.  The iteration
  * count k is unchanged, so the next episode boundary couples these objects.
  * Lets a caller seed a scan from an earlier result or from a separate

@@ -28,7 +28,7 @@ EXPORTED = [
     "cpra_workspace_size", "cpra_plan_create", "cpra_submit_angles", "cpra_iterate", "cpra_read_objects",
     "cpra_assemble_volume", "cpra_destroy", "cpra_last_error", "cpra_iteration_count", "cpra_slice_cells",
     "cpra_coupling_table", "cpra_set_kernel_timing", "cpra_kernel_timing", "cpra_load_objects",
-    "cpra_iterate_batch",
+    "cpra_iterate_batch", "cpra_prereconstruct", "cpra_sweep", "cpra_merge",
 ]
 
 
@@ -45,6 +45,7 @@ class Params(ctypes.Structure):
         ("real_type", ctypes.c_int32),
         ("amp_type", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
+        ("n_guess", ctypes.c_int32),
     ]
 
 
@@ -75,6 +76,9 @@ def load():
     lib.cpra_assemble_volume.argtypes = [c.c_void_p, c.c_void_p]
     lib.cpra_destroy.argtypes = [c.c_void_p]
     lib.cpra_iterate_batch.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_int32, c.c_double]
+    lib.cpra_prereconstruct.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_double, c.c_void_p]
+    lib.cpra_sweep.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_double, c.c_void_p]
+    lib.cpra_merge.argtypes = [c.c_void_p, c.c_int32, c.c_void_p, c.c_void_p]
     lib.cpra_last_error.argtypes = [c.c_void_p]
     lib.cpra_last_error.restype = c.c_char_p
     lib.cpra_iteration_count.argtypes = [c.c_void_p, P(c.c_int64)]
@@ -106,7 +110,7 @@ def iterate_batch(plans, n_iter, algo=HIO, beta=0.9):
 
 
 def make_params(N, Np, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=WRAP_MIRROR, positivity=True,
-                real=REAL_F32, amp=AMP_F32, seed=0):
+                real=REAL_F32, amp=AMP_F32, seed=0, n_guess=1):
     p = Params()
     p.struct_size = ctypes.sizeof(Params)
     p.N, p.Np = int(N), int(Np)
@@ -120,6 +124,7 @@ def make_params(N, Np, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=WRAP_MIR
     p.n_ei, p.wrap, p.positivity = int(n_ei), int(wrap), int(bool(positivity))
     p.real_type, p.amp_type = int(real), int(amp)
     p.seed = int(seed) % (1 << 64)
+    p.n_guess = int(n_guess)
     return p
 
 
@@ -153,12 +158,13 @@ class Plan:
     """One scan on the current device: owns a torch workspace tensor and a library plan."""
 
     def __init__(self, N, Np, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=WRAP_MIRROR, positivity=True,
-                 real=REAL_F32, amp=AMP_F32, seed=0, stream=None, device=None):
+                 real=REAL_F32, amp=AMP_F32, seed=0, stream=None, device=None, n_guess=1):
         import torch
         self.torch = torch
         lib = load()
-        self.params = make_params(N, Np, theta, alpha, n_ei, wrap, positivity, real, amp, seed)
+        self.params = make_params(N, Np, theta, alpha, n_ei, wrap, positivity, real, amp, seed, n_guess)
         self.N, self.Np = int(N), int(Np)
+        self.R = max(1, int(n_guess))
         self.real = real
         self.dtype = torch.float64 if real == REAL_F64 else torch.float32
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -215,16 +221,42 @@ class Plan:
         _check(st, self.handle)
 
     def iterate(self, n_iter, algo=HIO, beta=0.9, errors=False):
-        err = np.zeros((n_iter, self.Np), np.float64) if errors else None
+        """Jacobi step B; returns E_F (n_iter, Np), or (n_iter, n_guess * Np) for several guesses."""
+        err = np.zeros((n_iter, self.R * self.Np), np.float64) if errors else None
         st = load().cpra_iterate(self.handle, int(n_iter), int(algo), float(beta),
                                  None if err is None else err.ctypes.data)
         _check(st, self.handle)
         return err
 
+    def _obj_shape(self):
+        return (self.Np, self.N, self.N) if self.R == 1 else (self.R, self.Np, self.N, self.N)
+
+    def prereconstruct(self, n_iter, algo=HIO, beta=0.9, errors=False):
+        """Step A on angle 0 of every guess; returns E_F (n_guess, n_iter) if errors."""
+        err = np.zeros((self.R, n_iter), np.float64) if errors else None
+        _check(load().cpra_prereconstruct(self.handle, int(n_iter), int(algo), float(beta),
+                                          None if err is None else err.ctypes.data), self.handle)
+        return err
+
+    def sweep(self, n_episodes, algo=HIO, beta=0.9, errors=False):
+        """Consecutive step B; returns E_F (n_episodes, n_guess, Np, n_ei) if errors."""
+        err = np.zeros((n_episodes, self.R, self.Np, self.params.n_ei), np.float64) if errors else None
+        _check(load().cpra_sweep(self.handle, int(n_episodes), int(algo), float(beta),
+                                 None if err is None else err.ctypes.data), self.handle)
+        return err
+
+    def merge(self, n_best):
+        """Step C; returns (kept guesses in rank order, inverted flags)."""
+        kept = np.zeros(n_best, np.int32)
+        inv = np.zeros(n_best, np.int32)
+        _check(load().cpra_merge(self.handle, int(n_best), kept.ctypes.data, inv.ctypes.data), self.handle)
+        return kept, inv.astype(bool)
+
     def objects(self, out=None):
+        """Current iterates: (Np, N, N), or (n_guess, Np, N, N) for several guesses."""
         torch = self.torch
         if out is None:
-            out = torch.empty((self.Np, self.N, self.N), dtype=self.dtype, device=self.device)
+            out = torch.empty(self._obj_shape(), dtype=self.dtype, device=self.device)
         self._enter()
         _check(load().cpra_read_objects(self.handle, ctypes.c_void_p(out.data_ptr()), PTR_DEVICE), self.handle)
         self._leave(out)
@@ -235,13 +267,13 @@ class Plan:
         torch = self.torch
         if isinstance(objects, np.ndarray):
             a = np.ascontiguousarray(objects, dtype=np.float64 if self.real == REAL_F64 else np.float32)
-            if a.shape != (self.Np, self.N, self.N):
-                raise ValueError("objects must be (Np, N, N)")
+            if a.shape != self._obj_shape():
+                raise ValueError(f"objects must be {self._obj_shape()}")
             st = load().cpra_load_objects(self.handle, a.ctypes.data, PTR_HOST)
         else:
             a = objects.contiguous()
-            if a.dtype != self.dtype or tuple(a.shape) != (self.Np, self.N, self.N) or not a.is_cuda:
-                raise TypeError("objects must be a CUDA tensor of shape (Np, N, N) in the plan's precision")
+            if a.dtype != self.dtype or tuple(a.shape) != self._obj_shape() or not a.is_cuda:
+                raise TypeError(f"objects must be a CUDA tensor of shape {self._obj_shape()} in the plan's precision")
             self._enter()       # synchronises before returning
             st = load().cpra_load_objects(self.handle, ctypes.c_void_p(a.data_ptr()), PTR_DEVICE)
         _check(st, self.handle)

@@ -1,7 +1,9 @@
 // C ABI of the CPRA hot path: plan, workspace layout, kernel dispatch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <numeric>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -59,6 +61,9 @@ cpra_status validate(const cpra_params* p, std::string& msg) {
   if (p->struct_size != sizeof(cpra_params)) { msg = "params.struct_size mismatch"; return CPRA_ERR_ARG; }
   if (!size_supported(p->N)) { msg = "N must be 64, 128, 256, 512 or 1024"; return CPRA_ERR_UNSUPPORTED; }
   if (p->Np < 1) { msg = "Np must be >= 1"; return CPRA_ERR_ARG; }
+  if (p->n_guess < 0 || (int64_t)p->Np * std::max(1, p->n_guess) > (1 << 24)) {
+    msg = "n_guess must be >= 0 (0 = one) with n_guess * Np <= 2^24"; return CPRA_ERR_ARG;
+  }
   if (p->n_ei < 1) { msg = "n_ei must be >= 1"; return CPRA_ERR_ARG; }
   if (p->wrap != CPRA_WRAP_MIRROR && p->wrap != CPRA_WRAP_PLAIN) { msg = "bad wrap"; return CPRA_ERR_ARG; }
   if (p->real_type != CPRA_REAL_F32 && p->real_type != CPRA_REAL_F64) { msg = "bad real_type"; return CPRA_ERR_ARG; }
@@ -82,25 +87,26 @@ cpra_status validate(const cpra_params* p, std::string& msg) {
 
 Layout layout_of(const cpra_params* p) {
   const size_t N = p->N, Np = p->Np, H = N / 2;
+  const size_t S = Np * (size_t)std::max(1, p->n_guess);   // slots: guess r, angle n at r * Np + n
   const size_t rs = p->real_type == CPRA_REAL_F64 ? 8 : 4;
   const size_t cs = 2 * rs;
   const size_t aps = p->real_type == CPRA_REAL_F64 ? 16 : (p->amp_type == CPRA_AMP_F16 ? 4 : 8);
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
-  L.P = take(Np * N * H * cs);
-  L.Pmid = take(Np * N * H * cs);
-  L.g0 = take(Np * N * N * rs);
-  L.g1 = take(Np * N * N * rs);
+  L.P = take(S * N * H * cs);
+  L.Pmid = take(S * N * H * cs);
+  L.g0 = take(S * N * N * rs);
+  L.g1 = take(S * N * N * rs);
   L.A2 = take(Np * N * H * aps);
   L.ampscale = take(Np * rs);
   L.maskw = take(Np * N * mask_words_per_row(p->N) * 4);
   L.den = take(Np * 8);
   L.tw = take((3 * N + 3 * H) * cs);   // twiddle tables (kernels.hpp, TwLayout)
-  L.coup = take(Np * sizeof(cpra::Coupling));
-  L.alist = take(Np * 4);
-  L.errpart = take((size_t)kErrSlots * Np * col_tiles(p->N) * 8);
-  L.errhist = take((size_t)kErrSlots * Np * 8);
+  L.coup = take(S * sizeof(cpra::Coupling));
+  L.alist = take(S * 4);
+  L.errpart = take((size_t)kErrSlots * S * col_tiles(p->N) * 8);
+  L.errhist = take((size_t)kErrSlots * S * 8);
   L.flags = take(256);
   L.stage_I = take((size_t)kStageAngles * N * N * 4);
   L.stage_S = take((size_t)kStageAngles * N * N);
@@ -110,6 +116,7 @@ Layout layout_of(const cpra_params* p) {
   L.zc = stepd_chunk(p->N);
   L.plane = take((size_t)L.zc * N * N * cs);
   L.prep_part = take(Np * cpra::kPrepBlocks * 12);
+  L.mtab = take(S * 3 * 8 + S * 4 * 4 + (S / Np) * 64 + 256);   // step C tables
   L.total = o;
   return L;
 }
@@ -157,12 +164,21 @@ Ops ops_of(const cpra_params& p) {
 }
 
 cpra_status upload_tables(cpra_plan_t pl) {
-  const int Np = pl->p.Np;
-  cpra_host::coupling_table(Np, pl->present.data(), pl->p.alpha, pl->p.wrap == CPRA_WRAP_MIRROR, pl->coup_h);
+  const int Np = pl->p.Np, R = pl->R;
+  // one ring per guess: the table of the Np angles, offset to each guess's slots
+  std::vector<cpra_host::Coupling> one;
+  cpra_host::coupling_table(Np, pl->present.data(), pl->p.alpha, pl->p.wrap == CPRA_WRAP_MIRROR, one);
+  pl->coup_h.resize((size_t)R * Np);
   pl->alist_h.clear();
-  for (int n = 0; n < Np; ++n)
-    if (pl->present[n]) pl->alist_h.push_back(n);
-  HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.coup, pl->coup_h.data(), Np * sizeof(cpra::Coupling),
+  for (int r = 0; r < R; ++r)
+    for (int n = 0; n < Np; ++n) {
+      cpra_host::Coupling c = one[n];
+      c.left += r * Np;
+      c.right += r * Np;
+      pl->coup_h[(size_t)r * Np + n] = c;
+      if (pl->present[n]) pl->alist_h.push_back(r * Np + n);
+    }
+  HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.coup, pl->coup_h.data(), pl->coup_h.size() * sizeof(cpra::Coupling),
                             hipMemcpyHostToDevice, pl->stream));
   if (!pl->alist_h.empty())
     HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist, pl->alist_h.data(), pl->alist_h.size() * 4,
@@ -200,6 +216,8 @@ cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t 
   cpra_plan_t pl = new (std::nothrow) cpra_plan_s();
   if (!pl) return fail(nullptr, CPRA_ERR_OOM, "host allocation failed");
   pl->p = *params;
+  pl->R = std::max(1, params->n_guess);
+  pl->p.n_guess = pl->R;
   pl->theta.resize(params->Np);
   for (int n = 0; n < params->Np; ++n)
     pl->theta[n] = params->theta ? params->theta[n] : cpra_host::default_theta(n, params->Np);
@@ -257,8 +275,8 @@ cpra_status cpra_submit_angles(cpra_plan_t pl, int32_t first, int32_t count, con
   const size_t NN = (size_t)N * N;
   Ops ops = ops_of(pl->p);
   HIPCHK(pl, hipMemsetAsync(pl->ws + pl->L.flags, 0, 4, pl->stream));
-  std::vector<int32_t> ids(count);
-  for (int i = 0; i < count; ++i) ids[i] = first + i;
+  // slots to initialise: every guess's copy of each submitted angle, grouped per staging chunk
+  const int R = pl->R, Np = pl->p.Np;
   // host inputs are staged through the workspace a few angles at a time;
   // device inputs go out in one launch of each kernel
   const int chunk = ptr_kind == CPRA_PTR_HOST ? kStageAngles : count;
@@ -277,11 +295,14 @@ cpra_status cpra_submit_angles(cpra_plan_t pl, int32_t first, int32_t count, con
     }
     ops.prep(pl, dI, dS, first + c0, cn);
     LAUNCHCHK(pl);
-    // initial objects go into the buffer that holds the current iterate
-    HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist + 0, ids.data() + c0, cn * 4, hipMemcpyHostToDevice, pl->stream));
-    ops.init(pl, at<int>(pl, pl->L.alist), cn, pl->cur);
+    // initial objects of every guess go into the buffer that holds the current iterate
+    std::vector<int32_t> ids;
+    for (int r = 0; r < R; ++r)
+      for (int i = 0; i < cn; ++i) ids.push_back(r * Np + first + c0 + i);
+    HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, pl->stream));
+    ops.init(pl, at<int>(pl, pl->L.alist), (int)ids.size(), pl->cur);
     LAUNCHCHK(pl);
-    if (ptr_kind == CPRA_PTR_HOST) HIPCHK(pl, hipStreamSynchronize(pl->stream));
+    HIPCHK(pl, hipStreamSynchronize(pl->stream));   // ids is rebuilt for the next chunk
   }
   int flag = 0;
   HIPCHK(pl, hipMemcpyAsync(&flag, pl->ws + pl->L.flags, 4, hipMemcpyDeviceToHost, pl->stream));
@@ -309,7 +330,7 @@ static cpra_status step_once(cpra_plan_t pl, const Ops& ops, int32_t algo, doubl
   const int nact = (int)pl->alist_h.size();
   const bool estimate = ((pl->k + 1) % pl->p.n_ei) == 0;
   const int mode = estimate ? 2 : (algo == CPRA_HIO ? 1 : 2);
-  ops.step(pl, nact, boundary, mode, beta, nullptr);
+  ops.step(pl, at<int>(pl, pl->L.alist), nact, boundary, false, mode, beta, nullptr);
   LAUNCHCHK(pl);
   if (boundary) pl->cur ^= 1;
   pl->k += 1;
@@ -357,8 +378,9 @@ cpra_status cpra_iterate(cpra_plan_t pl, int32_t n_iter, int32_t algo, double be
     if (!any) return fail(pl, CPRA_ERR_STATE, "no angle has been submitted");
   }
   Ops ops = ops_of(pl->p);
+  const size_t Sl = (size_t)Np * pl->R;
   if (err_out)
-    for (size_t i = 0; i < (size_t)n_iter * Np; ++i) err_out[i] = NAN;
+    for (size_t i = 0; i < (size_t)n_iter * Sl; ++i) err_out[i] = NAN;
   int slot = 0, slot_base = 0;
   // reduce the pending error slots with the angle list they were computed with
   auto flush = [&]() -> cpra_status {
@@ -367,14 +389,14 @@ cpra_status cpra_iterate(cpra_plan_t pl, int32_t n_iter, int32_t algo, double be
     const int tot = slot * nact;
     k_err_reduce<<<(tot + 255) / 256, 256, 0, pl->stream>>>(at<double>(pl, pl->L.errpart), at<double>(pl, pl->L.den),
                                                             at<int>(pl, pl->L.alist), nact, pl->ntiles, slot,
-                                                            at<double>(pl, pl->L.errhist));
+                                                            pl->p.Np, at<double>(pl, pl->L.errhist));
     LAUNCHCHK(pl);
     pl->errhist_h.resize(tot);
     HIPCHK(pl, hipMemcpyAsync(pl->errhist_h.data(), pl->ws + pl->L.errhist, tot * 8, hipMemcpyDeviceToHost, pl->stream));
     HIPCHK(pl, hipStreamSynchronize(pl->stream));
     for (int s = 0; s < slot; ++s)
       for (int ai = 0; ai < nact; ++ai)
-        err_out[(size_t)(slot_base + s) * Np + pl->alist_h[ai]] = pl->errhist_h[(size_t)s * nact + ai];
+        err_out[(size_t)(slot_base + s) * Sl + pl->alist_h[ai]] = pl->errhist_h[(size_t)s * nact + ai];
     slot_base += slot;
     slot = 0;
     return CPRA_OK;
@@ -395,7 +417,7 @@ cpra_status cpra_iterate(cpra_plan_t pl, int32_t n_iter, int32_t algo, double be
     const bool estimate = ((pl->k + 1) % pl->p.n_ei) == 0;
     const int mode = estimate ? 2 : (algo == CPRA_HIO ? 1 : 2);
     double* ep = err_out ? at<double>(pl, pl->L.errpart) + (size_t)slot * nact * pl->ntiles : nullptr;
-    ops.step(pl, nact, boundary, mode, beta, ep);
+    ops.step(pl, at<int>(pl, pl->L.alist), nact, boundary, false, mode, beta, ep);
     LAUNCHCHK(pl);
     if (boundary) pl->cur ^= 1;
     pl->k += 1;
@@ -410,6 +432,209 @@ cpra_status cpra_iterate(cpra_plan_t pl, int32_t n_iter, int32_t algo, double be
   return CPRA_OK;
 }
 
+namespace {
+
+// slots of angle i in every guess at alist + i * R (the order of the consecutive sweep)
+cpra_status upload_sweep_lists(cpra_plan_t pl) {
+  const int Np = pl->p.Np, R = pl->R;
+  std::vector<int32_t> v((size_t)Np * R);
+  for (int i = 0; i < Np; ++i)
+    for (int r = 0; r < R; ++r) v[(size_t)i * R + r] = r * Np + i;
+  HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist, v.data(), v.size() * 4, hipMemcpyHostToDevice, pl->stream));
+  HIPCHK(pl, hipStreamSynchronize(pl->stream));
+  pl->tables_dirty = true;   // cpra_iterate rebuilds its own list
+  return CPRA_OK;
+}
+
+// n_it iterations of the R listed slots (one angle of every guess), in place; with `couple` the
+// first iteration starts from Eq. 4 over the neighbours' current objects; the last writes the
+// estimate.  err (R x n_it, row per slot) receives E_F when non-NULL.
+cpra_status run_po(cpra_plan_t pl, const Ops& ops, const int* d_list, int n_it, bool couple, int algo,
+                   double beta, double* err) {
+  const int R = pl->R;
+  double* errpart = at<double>(pl, pl->L.errpart);
+  std::vector<double> hist;
+  for (int it = 0; it < n_it; ++it) {
+    const int mode = it == n_it - 1 ? 2 : (algo == CPRA_HIO ? 1 : 2);
+    double* ep = err ? errpart + (size_t)(it % kErrSlots) * R * pl->ntiles : nullptr;
+    ops.step(pl, d_list, R, couple && it == 0, true, mode, beta, ep);
+    LAUNCHCHK(pl);
+    if (err && (it % kErrSlots == kErrSlots - 1 || it == n_it - 1)) {
+      const int ns = it % kErrSlots + 1;
+      k_err_reduce<<<(ns * R + 255) / 256, 256, 0, pl->stream>>>(errpart, at<double>(pl, pl->L.den), d_list, R,
+                                                                  pl->ntiles, ns, pl->p.Np,
+                                                                  at<double>(pl, pl->L.errhist));
+      LAUNCHCHK(pl);
+      hist.resize((size_t)ns * R);
+      HIPCHK(pl, hipMemcpyAsync(hist.data(), pl->ws + pl->L.errhist, hist.size() * 8, hipMemcpyDeviceToHost,
+                                pl->stream));
+      HIPCHK(pl, hipStreamSynchronize(pl->stream));
+      for (int q = 0; q < ns; ++q)
+        for (int r = 0; r < R; ++r) err[(size_t)r * n_it + (it - ns + 1 + q)] = hist[(size_t)q * R + r];
+    }
+  }
+  return CPRA_OK;
+}
+
+cpra_status check_algo(cpra_plan_t pl, int32_t algo, double beta) {
+  if (algo != CPRA_HIO && algo != CPRA_ER) return fail(pl, CPRA_ERR_ARG, "bad algo");
+  if (!std::isfinite(beta)) return fail(pl, CPRA_ERR_ARG, "beta must be finite");
+  return CPRA_OK;
+}
+
+bool all_landed(cpra_plan_t pl) {
+  return std::all_of(pl->landed.begin(), pl->landed.end(), [](uint8_t v) { return v != 0; });
+}
+
+}  // namespace
+
+cpra_status cpra_prereconstruct(cpra_plan_t pl, int32_t n_iter, int32_t algo, double beta, double* err_out) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
+  if (n_iter < 1) return fail(pl, CPRA_ERR_ARG, "n_iter < 1");
+  cpra_status st = check_algo(pl, algo, beta);
+  if (st != CPRA_OK) return st;
+  if (!pl->landed[0]) return fail(pl, CPRA_ERR_STATE, "angle 0 has not been submitted");
+  Ops ops = ops_of(pl->p);
+  st = upload_sweep_lists(pl);
+  if (st != CPRA_OK) return st;
+  std::vector<double> e(err_out ? (size_t)pl->R * n_iter : 0);
+  st = run_po(pl, ops, at<int>(pl, pl->L.alist), n_iter, false, algo, beta, err_out ? e.data() : nullptr);
+  if (st != CPRA_OK) return st;
+  if (err_out) std::copy(e.begin(), e.end(), err_out);
+  return CPRA_OK;
+}
+
+cpra_status cpra_sweep(cpra_plan_t pl, int32_t n_episodes, int32_t algo, double beta, double* err_out) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
+  if (n_episodes < 0) return fail(pl, CPRA_ERR_ARG, "n_episodes < 0");
+  cpra_status st = check_algo(pl, algo, beta);
+  if (st != CPRA_OK) return st;
+  if (!all_landed(pl)) return fail(pl, CPRA_ERR_STATE, "the consecutive sweep needs every angle submitted");
+  if (pl->k % pl->p.n_ei != 0)
+    return fail(pl, CPRA_ERR_STATE, "the sweep starts at an episode boundary (k=%lld)", (long long)pl->k);
+  const int Np = pl->p.Np, R = pl->R, ne = pl->p.n_ei;
+  Ops ops = ops_of(pl->p);
+  pl->present = pl->landed;
+  st = upload_tables(pl);   // the full ring of every guess
+  if (st != CPRA_OK) return st;
+  st = upload_sweep_lists(pl);
+  if (st != CPRA_OK) return st;
+  std::vector<double> e(err_out ? (size_t)R * ne : 0);
+  for (int m = 0; m < n_episodes; ++m)
+    for (int i = 0; i < Np; ++i) {
+      st = run_po(pl, ops, at<int>(pl, pl->L.alist) + (size_t)i * R, ne, true, algo, beta,
+                  err_out ? e.data() : nullptr);
+      if (st != CPRA_OK) return st;
+      if (err_out)
+        for (int r = 0; r < R; ++r)
+          for (int it = 0; it < ne; ++it)
+            err_out[(((size_t)m * R + r) * Np + i) * ne + it] = e[(size_t)r * ne + it];
+    }
+  pl->k += (int64_t)n_episodes * ne;
+  return CPRA_OK;
+}
+
+cpra_status cpra_merge(cpra_plan_t pl, int32_t n_best, int32_t* kept, int32_t* inverted) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
+  const int Np = pl->p.Np, R = pl->R, N = pl->p.N;
+  if (n_best < 1 || n_best > R) return fail(pl, CPRA_ERR_ARG, "n_best must be in [1, %d]", R);
+  if (!all_landed(pl)) return fail(pl, CPRA_ERR_STATE, "the merge needs every angle submitted");
+  if (pl->k % pl->p.n_ei != 0)
+    return fail(pl, CPRA_ERR_STATE, "the merge needs an episode end (k=%lld)", (long long)pl->k);
+  const size_t S = (size_t)R * Np;
+  const int K = n_best;
+  Ops ops = ops_of(pl->p);
+  // device tables in the step-C region
+  char* mt = pl->ws + pl->L.mtab;
+  double* d_mom = reinterpret_cast<double*>(mt);
+  int* d_shift = reinterpret_cast<int*>(mt + S * 3 * 8);
+  int* d_list = d_shift + S * 2;
+  double* d_twin = reinterpret_cast<double*>(mt + S * 3 * 8 + S * 4 * 4);
+  int* d_small = reinterpret_cast<int*>(d_twin + 2 * R);   // keep (R), inverted (R), twin slots (R), twin shifts (2R)
+  // 1. episode error of every guess: pooled E_F of its current objects
+  std::vector<int32_t> all(S);
+  std::iota(all.begin(), all.end(), 0);
+  HIPCHK(pl, hipMemcpyAsync(d_list, all.data(), S * 4, hipMemcpyHostToDevice, pl->stream));
+  ops.colerr(pl, d_list, (int)S, at<double>(pl, pl->L.errpart));
+  LAUNCHCHK(pl);
+  k_err_reduce<<<(unsigned)((S + 255) / 256), 256, 0, pl->stream>>>(at<double>(pl, pl->L.errpart),
+                                                                      at<double>(pl, pl->L.den), d_list, (int)S,
+                                                                      pl->ntiles, 1, Np, at<double>(pl, pl->L.errhist));
+  LAUNCHCHK(pl);
+  std::vector<double> e(S), den(Np);
+  HIPCHK(pl, hipMemcpyAsync(e.data(), pl->ws + pl->L.errhist, S * 8, hipMemcpyDeviceToHost, pl->stream));
+  HIPCHK(pl, hipMemcpyAsync(den.data(), pl->ws + pl->L.den, Np * 8, hipMemcpyDeviceToHost, pl->stream));
+  HIPCHK(pl, hipStreamSynchronize(pl->stream));
+  double dsum = 0.0;
+  for (int n = 0; n < Np; ++n) dsum += den[n];
+  std::vector<double> E(R);
+  for (int r = 0; r < R; ++r) {
+    double num = 0.0;
+    for (int n = 0; n < Np; ++n) num += e[(size_t)r * Np + n] * e[(size_t)r * Np + n] * den[n];
+    E[r] = dsum > 0.0 ? std::sqrt(num / dsum) : std::sqrt(num);
+  }
+  // 2. the n_best guesses of lowest error, in rank order (ties keep guess order)
+  std::vector<int32_t> order(R);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return E[a] < E[b]; });
+  std::vector<int32_t> keep(order.begin(), order.begin() + K);
+  // 3. mass centres of the kept POs -> integer shifts floor(-c + 1/2)
+  std::vector<int32_t> list((size_t)K * Np);
+  for (int j = 0; j < K; ++j)
+    for (int n = 0; n < Np; ++n) list[(size_t)j * Np + n] = keep[j] * Np + n;
+  HIPCHK(pl, hipMemcpyAsync(d_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, pl->stream));
+  ops.moments(pl, d_list, K * Np, d_mom);
+  LAUNCHCHK(pl);
+  std::vector<double> mom((size_t)K * Np * 3);
+  HIPCHK(pl, hipMemcpyAsync(mom.data(), d_mom, mom.size() * 8, hipMemcpyDeviceToHost, pl->stream));
+  HIPCHK(pl, hipStreamSynchronize(pl->stream));
+  std::vector<int32_t> shift((size_t)K * Np * 2);
+  for (size_t q = 0; q < (size_t)K * Np; ++q) {
+    const double m0 = mom[3 * q];
+    const double cz = m0 != 0.0 ? mom[3 * q + 1] / m0 : 0.0, ct = m0 != 0.0 ? mom[3 * q + 2] / m0 : 0.0;
+    shift[2 * q] = (int32_t)std::floor(-cz + 0.5);
+    shift[2 * q + 1] = (int32_t)std::floor(-ct + 0.5);
+  }
+  // 4. twin test of every other kept guess against the best one, on PO 0
+  std::vector<int32_t> inv(K, 0);
+  if (K > 1) {
+    std::vector<int32_t> tsl(K), tsh(2 * K);
+    for (int j = 0; j < K; ++j) {
+      tsl[j] = keep[j] * Np;
+      tsh[2 * j] = shift[(size_t)2 * j * Np];
+      tsh[2 * j + 1] = shift[(size_t)2 * j * Np + 1];
+    }
+    HIPCHK(pl, hipMemcpyAsync(d_small + 2 * R, tsl.data(), K * 4, hipMemcpyHostToDevice, pl->stream));
+    HIPCHK(pl, hipMemcpyAsync(d_small + 3 * R, tsh.data(), 2 * K * 4, hipMemcpyHostToDevice, pl->stream));
+    ops.twin(pl, d_small + 2 * R, d_small + 3 * R, K, d_twin);
+    LAUNCHCHK(pl);
+    std::vector<double> tw(2 * K);
+    HIPCHK(pl, hipMemcpyAsync(tw.data(), d_twin, 2 * K * 8, hipMemcpyDeviceToHost, pl->stream));
+    HIPCHK(pl, hipStreamSynchronize(pl->stream));
+    for (int j = 1; j < K; ++j) inv[j] = tw[2 * j + 1] < tw[2 * j] ? 1 : 0;
+  }
+  // 5. average into guess 0's slots (through the Pmid scratch) and rebuild their row spectra
+  HIPCHK(pl, hipMemcpyAsync(d_small, keep.data(), K * 4, hipMemcpyHostToDevice, pl->stream));
+  HIPCHK(pl, hipMemcpyAsync(d_small + R, inv.data(), K * 4, hipMemcpyHostToDevice, pl->stream));
+  HIPCHK(pl, hipMemcpyAsync(d_shift, shift.data(), shift.size() * 4, hipMemcpyHostToDevice, pl->stream));
+  ops.merge_avg(pl, K, d_small, d_small + R, d_shift, pl->ws + pl->L.Pmid);
+  LAUNCHCHK(pl);
+  const size_t rs = pl->p.real_type == CPRA_REAL_F64 ? 8 : 4;
+  HIPCHK(pl, hipMemcpyAsync(pl->ws + (pl->cur ? pl->L.g1 : pl->L.g0), pl->ws + pl->L.Pmid, (size_t)Np * N * N * rs,
+                            hipMemcpyDeviceToDevice, pl->stream));
+  HIPCHK(pl, hipMemcpyAsync(d_list, all.data(), (size_t)Np * 4, hipMemcpyHostToDevice, pl->stream));
+  ops.reload(pl, d_list, Np, pl->cur);
+  LAUNCHCHK(pl);
+  HIPCHK(pl, hipStreamSynchronize(pl->stream));
+  pl->tables_dirty = true;
+  if (kept) std::copy(keep.begin(), keep.end(), kept);
+  if (inverted) std::copy(inv.begin(), inv.end(), inverted);
+  return CPRA_OK;
+}
+
 cpra_status cpra_load_objects(cpra_plan_t pl, const void* objects, int32_t ptr_kind) {
   if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
   if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
@@ -417,8 +642,9 @@ cpra_status cpra_load_objects(cpra_plan_t pl, const void* objects, int32_t ptr_k
   if (ptr_kind != CPRA_PTR_HOST && ptr_kind != CPRA_PTR_DEVICE) return fail(pl, CPRA_ERR_ARG, "bad ptr_kind");
   const int Np = pl->p.Np;
   std::vector<int32_t> ids;
-  for (int n = 0; n < Np; ++n)
-    if (pl->landed[n]) ids.push_back(n);
+  for (int r = 0; r < pl->R; ++r)
+    for (int n = 0; n < Np; ++n)
+      if (pl->landed[n]) ids.push_back(r * Np + n);
   if (ids.empty()) return fail(pl, CPRA_ERR_STATE, "no angle has been submitted");
   const size_t plane = (size_t)pl->p.N * pl->p.N * (pl->p.real_type == CPRA_REAL_F64 ? 8 : 4);
   char* dst = pl->ws + (pl->cur ? pl->L.g1 : pl->L.g0);
@@ -439,7 +665,7 @@ cpra_status cpra_read_objects(cpra_plan_t pl, void* out, int32_t ptr_kind) {
   if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
   if (!out) return fail(pl, CPRA_ERR_ARG, "out is NULL");
   if (ptr_kind != CPRA_PTR_HOST && ptr_kind != CPRA_PTR_DEVICE) return fail(pl, CPRA_ERR_ARG, "bad ptr_kind");
-  const size_t bytes = (size_t)pl->p.Np * pl->p.N * pl->p.N * (pl->p.real_type == CPRA_REAL_F64 ? 8 : 4);
+  const size_t bytes = (size_t)pl->R * pl->p.Np * pl->p.N * pl->p.N * (pl->p.real_type == CPRA_REAL_F64 ? 8 : 4);
   const char* src = pl->ws + (pl->cur ? pl->L.g1 : pl->L.g0);
   HIPCHK(pl, hipMemcpyAsync(out, src, bytes, ptr_kind == CPRA_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
                             pl->stream));

@@ -8,13 +8,14 @@
 #include "../../include/cpra.h"
 #include "host_geom.hpp"
 #include "kernels.hpp"
+#include "merge.hpp"
 #include "stepd.hpp"
 
 namespace cpra_impl {
 
 struct Layout {
   size_t P, Pmid, g0, g1, A2, ampscale, maskw, den, tw, coup, alist, errpart, errhist, flags, stage_I,
-      stage_S, csr_ptr, csr_ent, cnt_inv, plane, prep_part, total;
+      stage_S, csr_ptr, csr_ent, cnt_inv, plane, prep_part, mtab, total;
   int zc;   // z-planes per step-D chunk
 };
 
@@ -22,6 +23,7 @@ struct Layout {
 
 struct cpra_plan_s {
   cpra_params p{};
+  int R = 1;                   // guesses (independent reconstructions); slot r * Np + n
   std::vector<double> theta;
   cpra_impl::Layout L{};
   char* ws = nullptr;
@@ -63,9 +65,13 @@ struct Ops {
   void (*twiddles)(cpra_plan_t);
   void (*prep)(cpra_plan_t, const float*, const uint8_t*, int, int);
   void (*init)(cpra_plan_t, const int*, int, int);
-  void (*step)(cpra_plan_t, int, bool, int, double, double*);
+  void (*step)(cpra_plan_t, const int*, int, bool, bool, int, double, double*);
   void (*assemble)(cpra_plan_t, void*);
   void (*reload)(cpra_plan_t, const int*, int, int);
+  void (*colerr)(cpra_plan_t, const int*, int, double*);
+  void (*moments)(cpra_plan_t, const int*, int, double*);
+  void (*twin)(cpra_plan_t, const int*, const int*, int, double*);
+  void (*merge_avg)(cpra_plan_t, int, const int*, const int*, const int*, void*);
 };
 
 template <int N, typename T, typename AP>
@@ -92,22 +98,24 @@ struct Impl {
     if constexpr (CG::S == 2)
       k_col_pair<N, T, AP, 1, false><<<gc, bc, 0, pl->stream>>>(
           nullptr, at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2), at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw),
-          d_list, nullptr, 0, nullptr, CG::TILES, pl->p.seed);
+          d_list, nullptr, pl->p.Np, nullptr, CG::TILES, pl->p.seed);
     else
       k_col<N, T, AP, 1, false><<<gc, bc, 0, pl->stream>>>(
           nullptr, at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2), at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw),
-          d_list, nullptr, 0, nullptr, CG::TILES, pl->p.seed);
+          d_list, nullptr, pl->p.Np, nullptr, CG::TILES, pl->p.seed);
     T* g = at<T>(pl, gbuf ? pl->L.g1 : pl->L.g0);
     dim3 gr(N / RG::RPB, count), br(RG::T * RG::RPB);
     k_row<N, T><<<gr, br, 0, pl->stream>>>(at<C>(pl, pl->L.Pmid), at<C>(pl, pl->L.P), g, g,
-                                          at<uint32_t>(pl, pl->L.maskw), at<C>(pl, pl->L.tw), d_list, nullptr, 0,
-                                          0, (T)0, pl->p.positivity);
+                                          at<uint32_t>(pl, pl->L.maskw), at<C>(pl, pl->L.tw), d_list, nullptr,
+                                          pl->p.Np, 0, (T)0, pl->p.positivity);
   }
-  static void step(cpra_plan_t pl, int nact, bool couple, int mode, double beta, double* errpart) {
+  // one iteration of the listed slots; couple: Eq. 4 on the way in, from buffer cur into the other
+  // buffer (Jacobi) or, with inplace, within buffer cur (the neighbours must not be listed)
+  static void step(cpra_plan_t pl, const int* al, int nact, bool couple, bool inplace, int mode, double beta,
+                   double* errpart) {
     using CG = ColGeom<N>;
     using RG = RowGeom<N>;
     dim3 gc(CG::TILES, nact), bc(CG::R1 * CG::C);
-    const int* al = at<int>(pl, pl->L.alist);
     const cpra::Coupling* cp = at<cpra::Coupling>(pl, pl->L.coup);
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
     if (pl->timing) {
@@ -116,7 +124,7 @@ struct Impl {
     }
     auto launch = [&](auto kern, double* ep) {
       kern<<<gc, bc, 0, pl->stream>>>(at<C>(pl, pl->L.P), at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2),
-                                      at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw), al, cp, couple ? 1 : 0, ep,
+                                      at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw), al, cp, pl->p.Np, ep,
                                       CG::TILES, 0);
     };
     if constexpr (CG::S == 2) {
@@ -138,12 +146,36 @@ struct Impl {
     }
     if (e1) (void)hipEventRecord(e1, pl->stream);
     T* gin = at<T>(pl, pl->cur ? pl->L.g1 : pl->L.g0);
-    T* gout = couple ? at<T>(pl, pl->cur ? pl->L.g0 : pl->L.g1) : gin;
+    T* gout = (couple && !inplace) ? at<T>(pl, pl->cur ? pl->L.g0 : pl->L.g1) : gin;
     dim3 gr(N / RG::RPB, nact), br(RG::T * RG::RPB);
     auto row = couple ? k_row<N, T, true> : k_row<N, T, false>;
     row<<<gr, br, 0, pl->stream>>>(at<C>(pl, pl->L.Pmid), at<C>(pl, pl->L.P), gin, gout, at<uint32_t>(pl, pl->L.maskw),
-                                   at<C>(pl, pl->L.tw), al, cp, couple ? 1 : 0, mode, (T)beta, pl->p.positivity);
+                                   at<C>(pl, pl->L.tw), al, cp, pl->p.Np, mode, (T)beta, pl->p.positivity);
     if (e2) (void)hipEventRecord(e2, pl->stream);
+  }
+  // E_F partials of the current iterates of the listed slots (column pass without coupling; its
+  // Pmid output is scratch)
+  static void colerr(cpra_plan_t pl, const int* al, int nact, double* errpart) {
+    using CG = ColGeom<N>;
+    dim3 gc(CG::TILES, nact), bc(CG::R1 * CG::C);
+    auto kern = [&]() {
+      if constexpr (CG::S == 2) return k_col_pair<N, T, AP, 0, true, false>;
+      else return k_col<N, T, AP, 0, true, false>;
+    }();
+    kern<<<gc, bc, 0, pl->stream>>>(at<C>(pl, pl->L.P), at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2),
+                                    at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw), al, nullptr, pl->p.Np, errpart,
+                                    CG::TILES, 0);
+  }
+  static void moments(cpra_plan_t pl, const int* list, int count, double* out) {
+    k_moments<N, T><<<count, 256, 0, pl->stream>>>(at<T>(pl, pl->cur ? pl->L.g1 : pl->L.g0), list, out);
+  }
+  static void twin(cpra_plan_t pl, const int* slot, const int* shift, int count, double* out) {
+    k_twin_dist<N, T><<<count, 256, 0, pl->stream>>>(at<T>(pl, pl->cur ? pl->L.g1 : pl->L.g0), slot, shift, out);
+  }
+  static void merge_avg(cpra_plan_t pl, int K, const int* keep, const int* inv, const int* shift, void* out) {
+    k_merge_avg<N, T><<<dim3(N, pl->p.Np), 256, 0, pl->stream>>>(at<T>(pl, pl->cur ? pl->L.g1 : pl->L.g0),
+                                                                 pl->p.Np, K, keep, inv, shift,
+                                                                 reinterpret_cast<T*>(out));
   }
   // row spectra P = F_t(g) of the listed angles from the iterate in buffer gbuf
   static void reload(cpra_plan_t pl, const int* d_list, int count, int gbuf) {
@@ -151,7 +183,8 @@ struct Impl {
     T* g = at<T>(pl, gbuf ? pl->L.g1 : pl->L.g0);
     dim3 gr(N / RG::RPB, count), br(RG::T * RG::RPB);
     k_row<N, T><<<gr, br, 0, pl->stream>>>(nullptr, at<C>(pl, pl->L.P), g, g, at<uint32_t>(pl, pl->L.maskw),
-                                          at<C>(pl, pl->L.tw), d_list, nullptr, 0, 3, (T)0, pl->p.positivity);
+                                          at<C>(pl, pl->L.tw), d_list, nullptr, pl->p.Np, 3, (T)0,
+                                          pl->p.positivity);
   }
   static void assemble(cpra_plan_t pl, void* vol) {
     stepd_run<N, T>(at<C>(pl, pl->L.P), at<int>(pl, pl->L.csr_ptr), at<int>(pl, pl->L.csr_ent),
@@ -163,8 +196,10 @@ struct Impl {
 
 
 template <int N, typename T, typename AP> Ops ops_for() {
-  return Ops{&Impl<N, T, AP>::twiddles, &Impl<N, T, AP>::prep, &Impl<N, T, AP>::init, &Impl<N, T, AP>::step,
-             &Impl<N, T, AP>::assemble, &Impl<N, T, AP>::reload};
+  return Ops{&Impl<N, T, AP>::twiddles, &Impl<N, T, AP>::prep,    &Impl<N, T, AP>::init,
+             &Impl<N, T, AP>::step,     &Impl<N, T, AP>::assemble, &Impl<N, T, AP>::reload,
+             &Impl<N, T, AP>::colerr,   &Impl<N, T, AP>::moments,  &Impl<N, T, AP>::twin,
+             &Impl<N, T, AP>::merge_avg};
 }
 
 

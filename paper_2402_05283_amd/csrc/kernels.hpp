@@ -402,7 +402,7 @@ template <int N, typename T, typename AP, int MODE, bool ERR, bool CPL = false>
 __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
     k_col(const cx<T>* __restrict__ P, cx<T>* __restrict__ Pmid, const AP* __restrict__ A2,
           const T* __restrict__ ampscale, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
-          const Coupling* __restrict__ coup, int couple, double* __restrict__ errpart, int ntiles,
+          const Coupling* __restrict__ coup, int npd, double* __restrict__ errpart, int ntiles,
           uint64_t seed) {
   using Gm = ColGeom<N>;
   using TL = TwLayout<N>;
@@ -421,8 +421,9 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
   const int j = j0 + col;
   const size_t plane = (size_t)N * H;
   const T scale = (T)0.5 / ((T)N * (T)N);
-  const AP* An = A2 + (size_t)n * plane;
-  const T as = ampscale[n];
+  const int dn = n % npd;                  // data angle of slot n (slots r * npd + dn)
+  const AP* An = A2 + (size_t)dn * plane;
+  const T as = ampscale[dn];
   double err = 0.0;
   C g[R2];   // [q][d] after the forward transform (Q * R1 == R2)
 
@@ -621,7 +622,7 @@ template <int N, typename T, typename AP, int MODE, bool ERR, bool CPL = false>
 __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((amdgpu_waves_per_eu(4)))
     k_col_pair(const cx<T>* __restrict__ P, cx<T>* __restrict__ Pmid, const AP* __restrict__ A2,
                const T* __restrict__ ampscale, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
-               const Coupling* __restrict__ coup, int couple, double* __restrict__ errpart, int ntiles,
+               const Coupling* __restrict__ coup, int npd, double* __restrict__ errpart, int ntiles,
                uint64_t seed) {
   using Gm = ColGeom<N>;
   using TL = TwLayout<N>;
@@ -645,8 +646,9 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
   const int j = j0 + col;
   const size_t plane = (size_t)N * H;
   const T scale = (T)0.5 / ((T)N * (T)N);
-  const AP* An = A2 + (size_t)n * plane;
-  const T as = ampscale[n];
+  const int dn = n % npd;                  // data angle of slot n (slots r * npd + dn)
+  const AP* An = A2 + (size_t)dn * plane;
+  const T as = ampscale[dn];
   double err = 0.0;
   C g[R2];   // after the forward transform: G[c + R2 (k' + R2 sh)] at index k'
 
@@ -861,7 +863,7 @@ template <int N, typename T, bool CPL = false>
 __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((amdgpu_waves_per_eu(4)))
     k_row(const cx<T>* __restrict__ Pmid, cx<T>* __restrict__ P, const T* gin, T* gout,
           const uint32_t* __restrict__ maskw, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
-          const Coupling* __restrict__ coup, int couple, int mode, T beta, int positivity) {
+          const Coupling* __restrict__ coup, int npd, int mode, T beta, int positivity) {
   using Gm = RowGeom<N>;
   using TL = TwLayout<N>;
   using C = cx<T>;
@@ -956,7 +958,7 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
     });
     // ---- real-space update (pixels t = 2m and 2m+1 of x[m])
     uint32_t mwd[MW];
-    const uint32_t* Mrow = maskw + (((size_t)n * N + z) * TT + tau) * MW;
+    const uint32_t* Mrow = maskw + (((size_t)(n % npd) * N + z) * TT + tau) * MW;
     sfor<0, MW>([&](auto iv) CPRA_INLINE { mwd[decltype(iv)::value] = Mrow[decltype(iv)::value]; });
     Coupling cp{};
     if constexpr (CPL) cp = coup[n];
@@ -1045,7 +1047,7 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
 
 // ---------------------------------------------------------------- error reduce
 static __global__ void k_err_reduce(const double* __restrict__ errpart, const double* __restrict__ den,
-                             const int* __restrict__ alist, int nact, int ntiles, int nslots,
+                             const int* __restrict__ alist, int nact, int ntiles, int nslots, int npd,
                              double* __restrict__ hist) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nslots * nact) return;
@@ -1053,7 +1055,7 @@ static __global__ void k_err_reduce(const double* __restrict__ errpart, const do
   const double* p = errpart + ((size_t)slot * nact + ai) * ntiles;
   double s = 0.0;
   for (int t = 0; t < ntiles; ++t) s += p[t];
-  double d = den[alist[ai]];
+  double d = den[alist[ai] % npd];
   hist[i] = d > 0.0 ? sqrt(s / d) : sqrt(s);
 }
 
