@@ -1,5 +1,11 @@
 """The paper's schedule on the GPU against the schedule oracle: N_r guesses, step A
-pre-reconstruction, the consecutive sweep of step B and the step C merge (needs an MI355X)."""
+pre-reconstruction, the consecutive sweep of step B and the step C merge (needs an MI355X).
+
+Multi-iteration HIO runs amplify rounding differences chaotically (see the trajectory tests of the
+data-parallel path: FP32 rounding grows to percent level within tens of iterations, and the sweep
+compounds it along the ring), so FP64 plans are checked with HIO at 1e-10 and FP32 plans with ER,
+which contracts instead, at 1e-4.  The schedule's indexing and ordering do not depend on the
+algorithm."""
 import numpy as np
 import pytest
 
@@ -33,7 +39,7 @@ def _objects(torch, plan):
     return plan.objects().cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("real", [F32, F64])
+@pytest.mark.parametrize("real", [F64, F32])
 def test_guesses_jacobi(torch, real):
     """Several guesses under the data-parallel schedule: each guess is its own carousel with its own
     random start (phase stream r * Np + n)."""
@@ -41,53 +47,58 @@ def test_guesses_jacobi(torch, real):
     banner(f"guesses jacobi real={real}")
     plan, gs = _pair(scan, 3, real, n_ei=5)
     assert rel_l2(_objects(torch, plan), gs.g) <= (1e-6 if real == F32 else 1e-12)
-    plan.iterate(10)
-    gs.jacobi(2)
+    algo, beta = (1, 0.0) if real == F32 else (0, 0.9)
+    plan.iterate(10, algo, beta)
+    gs.jacobi(2, algo, beta)
     assert rel_l2(_objects(torch, plan), gs.g) <= (1e-4 if real == F32 else 1e-10)
 
 
-@pytest.mark.parametrize("real", [F32, F64])
+@pytest.mark.parametrize("real", [F64, F32])
 def test_prereconstruct_and_sweep(torch, real):
     scan = make_scan(1, N=64, Np=6)
     banner(f"step A + consecutive sweep real={real}")
     plan, gs = _pair(scan, 2, real, n_ei=3)
-    e_pre = plan.prereconstruct(8, errors=True)
-    o_pre = gs.prereconstruct(8)
+    algo, beta = (1, 0.0) if real == F32 else (0, 0.9)
+    e_pre = plan.prereconstruct(8, algo, beta, errors=True)
+    o_pre = gs.prereconstruct(8, algo, beta)
     tol = 1e-4 if real == F32 else 1e-10
     assert rel_l2(_objects(torch, plan), gs.g) <= tol
     assert rel_l2(e_pre, o_pre) <= tol
-    e_sw = plan.sweep(2, errors=True)
-    o_sw = gs.sweep(2)
+    e_sw = plan.sweep(2, algo, beta, errors=True)
+    o_sw = gs.sweep(2, algo, beta)
     assert plan.k == 6
     assert rel_l2(_objects(torch, plan), gs.g) <= tol
     assert rel_l2(e_sw, o_sw) <= tol
     plan.assemble_volume()                        # an episode end: step D is allowed
 
 
-@pytest.mark.parametrize("real", [F32, F64])
+@pytest.mark.parametrize("real", [F64, F32])
 def test_merge_constructed(torch, real):
-    """Guess 0 = true projections, guess 1 = their central inversions shifted by (2, -3) (same
-    intensities), guess 2 = noise: the merge keeps 0 and 1, undoes shift and inversion, and
-    returns the centred true projections, bit-for-bit the oracle's integer decisions."""
+    """Guess 0 = true projections, guess 1 = their central inversions shifted by (2, -3) plus a
+    little noise, guess 2 = noise: the merge keeps 0 and 1 in that order, undoes shift and
+    inversion, and averages; the integer decisions equal the oracle's."""
     from oracle import schedule as SC
     scan = make_scan(1, N=64, Np=4, keep_po=True)
     banner(f"merge constructed real={real}")
     plan, gs = _pair(scan, 3, real, n_ei=2)
     po = scan["po"].astype(np.float64)
-    objs = np.stack([po, np.array([SC.shift(SC.central_inversion(p), (2, -3)) for p in po]),
-                     np.random.default_rng(1).random(po.shape)])
+    rng = np.random.default_rng(1)
+    twin = np.array([SC.shift(SC.central_inversion(p), (2, -3)) for p in po])
+    twin += 1e-3 * po.max() * rng.random(po.shape)          # ranks the twin second (exact twins tie)
+    objs = np.stack([po, twin, rng.random(po.shape)])
     plan.load_objects(objs.astype(np.float32 if real == F32 else np.float64))
     gs.g[:] = objs
     plan.iterate(2)                               # reach an episode end (k = 2) ...
     plan.load_objects(objs.astype(np.float32 if real == F32 else np.float64))   # ... with these objects
     kept, inv = plan.merge(2)
     merged, okept, oinv = gs.merge(2)
+    assert okept == [0, 1] and oinv == [False, True]
     assert list(kept) == okept and list(inv) == oinv
     got = _objects(torch, plan)[0]
     assert rel_l2(got, merged) <= (1e-6 if real == F32 else 1e-12)
 
 
-@pytest.mark.parametrize("real", [F32, F64])
+@pytest.mark.parametrize("real", [F64, F32])
 def test_merge_after_sweep(torch, real):
     """The merge on real sweep output: integer decisions (ranking, shifts, inversions) equal the
     oracle's wherever their margins exceed the FP32 error of the objects; the merged episode
