@@ -374,6 +374,40 @@ def plain_comparison(cp, torch, scan, I, S, args, cpra_iter_ms):
     return out
 
 
+def paper_schedule(cp, torch, scan, I, S, args):
+    """The paper's own schedule on the same scan: N_r = 100 random guesses held at once, step A
+    (N_i^pre = 500 HIO iterations of PO 1), step B as the consecutive sweep (N_e = 1, N_ei = 2, the
+    paper's timing configuration), step C (merge of the N_l = 10 best guesses) and step D.
+    Sequential over angles, parallel over guesses."""
+    R, n_pre, n_e, n_ei, n_best = args.guesses, 500, 1, 2, 10
+    t = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = cp.Plan(N, NP, n_ei=n_ei, seed=scan["phase_seed"], n_guess=R)
+    plan.submit(0, I, S)
+    torch.cuda.synchronize()
+    t["submit"] = time.perf_counter() - t0
+    for name, fn in (("step_A", lambda: plan.prereconstruct(n_pre, cp.HIO, BETA)),
+                     ("step_B", lambda: plan.sweep(n_e, cp.HIO, BETA)),
+                     ("step_C", lambda: plan.merge(n_best)),
+                     ("step_D", lambda: plan.assemble_volume())):
+        t1 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        t[name] = time.perf_counter() - t1
+        if name == "step_C":
+            kept, inv = out
+    total = sum(t.values())
+    pits = R * (n_pre + NP * n_e * n_ei)
+    del plan
+    torch.cuda.empty_cache()
+    return {"guesses": R, "n_pre": n_pre, "episodes": n_e, "n_ei": n_ei, "n_best": n_best,
+            "seconds": {k: round(v, 4) for k, v in t.items()}, "total_s": round(total, 3),
+            "pattern_iterations": pits,
+            "pattern_iterations_per_s_steps_AB": round(pits / (t["step_A"] + t["step_B"]), 1),
+            "kept": [int(k) for k in kept], "inverted": [bool(i) for i in inv]}
+
+
 def quality_error_only(torch, obj, A_nat, den):
     err = []
     for c0 in range(0, obj.shape[0], 60):
@@ -394,6 +428,7 @@ def main():
     ap.add_argument("--serve-rounds", type=int, default=1, help="serving rounds (latency samples = scans x rounds)")
     ap.add_argument("--serve-fps", type=float, default=20.0, help="frames per second per scan")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain per-angle comparison")
+    ap.add_argument("--guesses", type=int, default=100, help="N_r of the paper-schedule leg (0: skip it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (the byte-counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -516,6 +551,9 @@ def main():
     if not args.no_compare and args.iters == ITERS and not args.amp16:
         print("[bench] plain per-angle comparison", file=sys.stderr, flush=True)
         out["vs_plain_per_angle"] = plain_comparison(cp, torch, scan, I, S, args, iter_ms)
+    if args.guesses > 0 and args.iters == ITERS and not args.amp16:
+        print(f"[bench] paper schedule, {args.guesses} guesses", file=sys.stderr, flush=True)
+        out["paper_schedule"] = paper_schedule(cp, torch, scan, I, S, args)
     if args.serve_scans > 0:
         out["latency_ms"] = serving_latency(cp, torch, scan, I, S, args)
         out["latency_ms"]["whole_scan_p50"] = round(float(np.percentile(lat, 50)) * 1e3, 2)
