@@ -42,7 +42,7 @@ import numpy as np
 from . import fft as F
 from .rng import initial_phases
 
-HIO, ER = 0, 1
+HIO, ER, RAAR = 0, 1, 2
 WRAP_MIRROR, WRAP_PLAIN = 0, 1
 
 
@@ -84,7 +84,16 @@ def fourier_error(G: np.ndarray, A: np.ndarray) -> float:
     return float(np.sqrt(num / den)) if den > 0 else float(np.sqrt(num))
 
 
+def support_projection(x, support, positivity):
+    """P_S: keep x on the support (and where x >= 0 with positivity), zero elsewhere."""
+    keep = support.astype(bool)
+    if positivity:
+        keep = keep & (x >= 0)
+    return np.where(keep, x, 0.0)
+
+
 def real_space_update(g, gp, support, algo, beta, positivity, estimate):
+    """gp = g' = P_M g (the modulus-projected iterate)."""
     gamma = support.astype(bool)
     if positivity:
         gamma = gamma & (gp >= 0)
@@ -92,7 +101,13 @@ def real_space_update(g, gp, support, algo, beta, positivity, estimate):
         return np.where(gamma, gp, 0.0)
     if algo == HIO:
         return np.where(gamma, gp, g - beta * gp)
-    raise ValueError("algo must be HIO or ER")
+    if algo == RAAR:
+        # Luke's relaxed averaged alternating reflections in operator form:
+        # g+ = beta/2 (R_S R_M + I) g + (1 - beta) P_M g, with R = 2P - I
+        rm = 2.0 * gp - g
+        rs_rm = 2.0 * support_projection(rm, support, positivity) - rm
+        return 0.5 * beta * (rs_rm + g) + (1.0 - beta) * gp
+    raise ValueError("algo must be HIO, ER or RAAR")
 
 
 def coupling_weights(Np, present, alpha, wrap):

@@ -112,3 +112,41 @@ def test_oracle_reconstructs_c1_reasonably(scan_c1):
     o.submit(0, scan_c1["I"], scan_c1["support"])
     err = o.iterate(200, C.HIO, 0.9)
     assert np.nanmean(err[-1]) < np.nanmean(err[0])
+
+
+def test_raar_closed_form_step():
+    """A = 2|F2 g| makes g' = 2g; RAAR's reflection is then 2g' - g = 3g, so per pixel the step is
+    2g where 3g meets the constraints (support, >= 0) and beta g + (1 - 2 beta) 2g elsewhere."""
+    rng = np.random.default_rng(4)
+    Np, N, beta = 2, 16, 0.9
+    g = rng.standard_normal((Np, N, N))
+    S = rng.uniform(size=(Np, N, N)) < 0.5
+    A = np.stack([2 * np.abs(C.forward(x)) for x in g])
+    o = _oracle_with_state(g, A, S)
+    o.iterate(1, C.RAAR, beta)
+    inside = S & (3 * g >= 0)
+    exp = np.where(inside, 2 * g, beta * g + (1 - 2 * beta) * 2 * g)
+    assert np.abs(o.g - exp).max() <= 1e-12
+
+
+def test_raar_with_beta_one_is_hio_without_positivity():
+    """Douglas-Rachford (RAAR at beta = 1) and HIO with beta = 1 coincide when the only real-space
+    constraint is the support (Bauschke, Combettes and Luke 2002)."""
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal((2, 16, 16))
+    S = rng.uniform(size=(2, 16, 16)) < 0.4
+    A = np.stack([np.abs(C.forward(x)) * rng.uniform(0.5, 1.5, (16, 16)) for x in g])
+    a = _oracle_with_state(g, A, S, positivity=False)
+    b = _oracle_with_state(g, A, S, positivity=False)
+    a.iterate(5, C.RAAR, 1.0)
+    b.iterate(5, C.HIO, 1.0)
+    assert np.abs(a.g - b.g).max() <= 1e-12 * np.abs(b.g).max()
+
+
+def test_true_object_is_fixed_point_of_raar(scan_c1):
+    po = scan_c1["po"][:3]
+    S = scan_c1["support"][:3].astype(bool)
+    A = np.stack([np.abs(C.forward(x)) for x in po])
+    o = _oracle_with_state(po, A, S)
+    o.iterate(3, C.RAAR, 0.9)
+    assert np.abs(o.g - po).max() <= 1e-12 * po.max()
