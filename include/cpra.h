@@ -45,7 +45,7 @@ typedef enum {
   CPRA_ERR_DATA = -6          /* NaN or Inf in the intensities                */
 } cpra_status;
 
-enum { CPRA_HIO = 0, CPRA_ER = 1 };                  /* real-space update     */
+enum { CPRA_HIO = 0, CPRA_ER = 1, CPRA_RAAR = 2 };   /* real-space update     */
 enum { CPRA_WRAP_MIRROR = 0, CPRA_WRAP_PLAIN = 1 };  /* carousel seam rule    */
 enum { CPRA_REAL_F32 = 0, CPRA_REAL_F64 = 1 };       /* arithmetic precision  */
 enum { CPRA_AMP_F32 = 0, CPRA_AMP_F16 = 1 };         /* amplitude storage     */
@@ -111,7 +111,12 @@ cpra_status cpra_submit_angles(cpra_plan_t plan, int32_t first, int32_t count,
  * G = F2(g); E_F = sqrt(sum (|G|-A)^2 / sum A^2) over measured pixels;
  * G' = A G/|G|; g' = Re F2^-1(G'); gamma = support AND (g' >= 0);
  * HIO (algo CPRA_HIO): g <- g' on gamma, g - beta g' elsewhere;
- * ER (CPRA_ER): g <- g' on gamma, 0 elsewhere.  The last iteration of an
+ * ER (CPRA_ER): g <- g' on gamma, 0 elsewhere;
+ * RAAR (CPRA_RAAR, Luke's relaxed averaged alternating reflections, the
+ * paper's choice for the measured cell): g <- beta/2 (R_S R_M + 1) g +
+ * (1 - beta) P_M g with P_M g = g', R = 2P - 1 and P_S the support (and
+ * positivity) projection; per pixel g' where 2g' - g meets the constraints,
+ * beta g + (1 - 2 beta) g' elsewhere.  The last iteration of an
  * episode writes the estimate g' on gamma, 0 elsewhere.
  * Every guess runs the same schedule on its own ring of slots.
  * err_out: NULL, or host n_iter x (n_guess * Np) doubles receiving E_F per

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libcpra.so")
 CPRA_OK = 0
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_OOM", -3: "ERR_DEVICE", -4: "ERR_STATE", -5: "ERR_UNSUPPORTED",
           -6: "ERR_DATA"}
-HIO, ER = 0, 1
+HIO, ER, RAAR = 0, 1, 2
 WRAP_MIRROR, WRAP_PLAIN = 0, 1
 REAL_F32, REAL_F64 = 0, 1
 AMP_F32, AMP_F16 = 0, 1

@@ -29,6 +29,9 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// row-pass mode of a real-space update rule (episode estimates use mode 2)
+int mode_of(int32_t algo) { return algo == CPRA_HIO ? 1 : algo == CPRA_RAAR ? 4 : 2; }
+
 thread_local std::string g_create_error;
 
 
@@ -329,7 +332,7 @@ static cpra_status step_once(cpra_plan_t pl, const Ops& ops, int32_t algo, doubl
   }
   const int nact = (int)pl->alist_h.size();
   const bool estimate = ((pl->k + 1) % pl->p.n_ei) == 0;
-  const int mode = estimate ? 2 : (algo == CPRA_HIO ? 1 : 2);
+  const int mode = estimate ? 2 : mode_of(algo);
   ops.step(pl, at<int>(pl, pl->L.alist), nact, boundary, false, mode, beta, nullptr);
   LAUNCHCHK(pl);
   if (boundary) pl->cur ^= 1;
@@ -347,7 +350,7 @@ cpra_status cpra_iterate_batch(cpra_plan_t* plans, int32_t count, int32_t n_iter
       if (plans[j] == pl) return fail(pl, CPRA_ERR_ARG, "plan %d repeated at %d", j, i);
     if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
     if (n_iter < 0) return fail(pl, CPRA_ERR_ARG, "n_iter < 0");
-    if (algo != CPRA_HIO && algo != CPRA_ER) return fail(pl, CPRA_ERR_ARG, "bad algo");
+    if (algo != CPRA_HIO && algo != CPRA_ER && algo != CPRA_RAAR) return fail(pl, CPRA_ERR_ARG, "bad algo");
     if (!std::isfinite(beta)) return fail(pl, CPRA_ERR_ARG, "beta must be finite");
     bool any = false;
     for (int n = 0; n < pl->p.Np; ++n) any = any || pl->landed[n];
@@ -369,7 +372,7 @@ cpra_status cpra_iterate(cpra_plan_t pl, int32_t n_iter, int32_t algo, double be
   if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
   if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
   if (n_iter < 0) return fail(pl, CPRA_ERR_ARG, "n_iter < 0");
-  if (algo != CPRA_HIO && algo != CPRA_ER) return fail(pl, CPRA_ERR_ARG, "bad algo");
+  if (algo != CPRA_HIO && algo != CPRA_ER && algo != CPRA_RAAR) return fail(pl, CPRA_ERR_ARG, "bad algo");
   if (!std::isfinite(beta)) return fail(pl, CPRA_ERR_ARG, "beta must be finite");
   const int Np = pl->p.Np;
   {
@@ -415,7 +418,7 @@ cpra_status cpra_iterate(cpra_plan_t pl, int32_t n_iter, int32_t algo, double be
     }
     const int nact = (int)pl->alist_h.size();
     const bool estimate = ((pl->k + 1) % pl->p.n_ei) == 0;
-    const int mode = estimate ? 2 : (algo == CPRA_HIO ? 1 : 2);
+    const int mode = estimate ? 2 : mode_of(algo);
     double* ep = err_out ? at<double>(pl, pl->L.errpart) + (size_t)slot * nact * pl->ntiles : nullptr;
     ops.step(pl, at<int>(pl, pl->L.alist), nact, boundary, false, mode, beta, ep);
     LAUNCHCHK(pl);
@@ -455,7 +458,7 @@ cpra_status run_po(cpra_plan_t pl, const Ops& ops, const int* d_list, int n_it, 
   double* errpart = at<double>(pl, pl->L.errpart);
   std::vector<double> hist;
   for (int it = 0; it < n_it; ++it) {
-    const int mode = it == n_it - 1 ? 2 : (algo == CPRA_HIO ? 1 : 2);
+    const int mode = it == n_it - 1 ? 2 : mode_of(algo);
     double* ep = err ? errpart + (size_t)(it % kErrSlots) * R * pl->ntiles : nullptr;
     ops.step(pl, d_list, R, couple && it == 0, true, mode, beta, ep);
     LAUNCHCHK(pl);
@@ -477,7 +480,7 @@ cpra_status run_po(cpra_plan_t pl, const Ops& ops, const int* d_list, int n_it, 
 }
 
 cpra_status check_algo(cpra_plan_t pl, int32_t algo, double beta) {
-  if (algo != CPRA_HIO && algo != CPRA_ER) return fail(pl, CPRA_ERR_ARG, "bad algo");
+  if (algo != CPRA_HIO && algo != CPRA_ER && algo != CPRA_RAAR) return fail(pl, CPRA_ERR_ARG, "bad algo");
   if (!std::isfinite(beta)) return fail(pl, CPRA_ERR_ARG, "beta must be finite");
   return CPRA_OK;
 }

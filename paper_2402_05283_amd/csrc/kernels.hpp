@@ -854,7 +854,8 @@ __device__ __forceinline__ C partner_c(C v, int partner_lane_idx) {
 
 // Row pass over RPB rows of one angle, F1 threads per row.
 // MODE 0: initial guess (g <- g'); 1: HIO; 2: ER / episode estimate;
-// 3: reload (P <- F_t(g) from the iterate in gin; Pmid unused, g unchanged).
+// 3: reload (P <- F_t(g) from the iterate in gin; Pmid unused, g unchanged);
+// 4: RAAR.
 // Per row: C2R of Pmid (pre-processing, F2-point IDFT, twiddle, LDS
 // exchange, F1-point IDFT) -> g' in the space layout; real-space update with
 // the support bits and g; R2C back (F1-point DFT, twiddle, LDS exchange,
@@ -884,7 +885,7 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
   // the current iterate of this thread's pixels, fetched up front so that
   // its HBM latency overlaps the Pmid stream (HIO only)
   C gk[SPT][F1];
-  if (mode == 1) {
+  if (mode == 1 || mode == 4) {
     sfor<0, SPT>([&](auto jv) CPRA_INLINE {
       constexpr int jj = decltype(jv)::value;
       sfor<0, F1>([&](auto mv) CPRA_INLINE {
@@ -990,7 +991,16 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
               else rv = *reinterpret_cast<const C*>(gr + 2 * m);
               gkv = mk<C>(w0 * gkv.x + wl * lv.x + wr * rv.x, w0 * gkv.y + wl * lv.y + wr * rv.y);
             }
-            out = mk<C>(g0 ? gp.x : gkv.x - beta * gp.x, g1 ? gp.y : gkv.y - beta * gp.y);
+            if (mode == 4) {
+              // RAAR, pixel form of beta/2 (R_S R_M + I) + (1 - beta) P_M: g' where the
+              // reflection 2g' - g meets the constraints, beta g + (1 - 2 beta) g' elsewhere
+              const bool r0 = s0 && (!positivity || (T)2 * gp.x - gkv.x >= (T)0);
+              const bool r1 = s1 && (!positivity || (T)2 * gp.y - gkv.y >= (T)0);
+              const T c1 = (T)1 - (T)2 * beta;
+              out = mk<C>(r0 ? gp.x : beta * gkv.x + c1 * gp.x, r1 ? gp.y : beta * gkv.y + c1 * gp.y);
+            } else {
+              out = mk<C>(g0 ? gp.x : gkv.x - beta * gp.x, g1 ? gp.y : gkv.y - beta * gp.y);
+            }
           }
         }
         *reinterpret_cast<C*>(gout + rowr + 2 * m) = out;

@@ -275,6 +275,48 @@ def test_fp16_amplitudes_error_is_small(torch):
         assert r16 <= lim16
 
 
+@pytest.mark.parametrize("real", [F32, F64])
+@pytest.mark.parametrize("N", [64, 512])
+def test_raar_one_iteration(torch, N, real):
+    """RAAR (beta 0.9) from W_0 through the first, coupled iteration.  The GPU applies the pixel
+    form; the oracle the operator form.  A pixel whose reflection 2g' - g is within rounding of 0
+    may take either branch."""
+    import paper_2402_05283_amd as cp
+    from oracle import cpra as C
+    scan = make_scan(1, N=N, Np=5)
+    banner(f"raar one iteration N={N} real={real}")
+    _, obj, errs = run_gpu(scan, [(1, cp.RAAR, 0.9)], real=real)
+    o, oerrs = run_oracle(scan, [(1, C.RAAR, 0.9)])
+    amb = 1e-5 if real == F32 else 1e-12
+    num = den = 0.0
+    for n in range(scan["Np"]):
+        gp, gprev = o.last_gp[n], o.g_prev[n]
+        refl = 2 * gp - gprev
+        rms = np.sqrt(np.mean(refl ** 2))
+        ambiguous = (np.abs(refl) <= amb * rms) & o.S[n]
+        alt = 0.9 * gprev + (1 - 1.8) * gp
+        ok = np.isclose(obj[n], o.g[n], rtol=1e-3, atol=1e-3 * rms) | np.isclose(obj[n], alt, rtol=1e-3,
+                                                                                  atol=1e-3 * rms)
+        assert np.all(ok[ambiguous])
+        keep = ~ambiguous
+        num += float(np.sum((obj[n][keep] - o.g[n][keep]) ** 2))
+        den += float(np.sum(o.g[n][keep] ** 2))
+    assert np.sqrt(num / den) <= (1e-5 if real == F32 else 1e-12)
+    assert rel_l2(errs[0], oerrs[0]) <= (1e-5 if real == F32 else 1e-12)
+
+
+def test_raar_run_fp64(torch):
+    """30 RAAR iterations (three episodes, couplings and estimates) on the 64^3 / 16-angle scan."""
+    import paper_2402_05283_amd as cp
+    from oracle import cpra as C
+    scan = make_scan(1)
+    banner("raar 30 iterations fp64")
+    _, obj, errs = run_gpu(scan, [(30, cp.RAAR, 0.9)], real=F64)
+    o, oerrs = run_oracle(scan, [(30, C.RAAR, 0.9)])
+    assert rel_l2(obj, o.g) <= 1e-6
+    assert rel_l2(errs[0], oerrs[0]) <= 1e-6
+
+
 def test_iterate_batch_matches_alone(torch):
     """cpra_iterate_batch: three scans of different N and Np, each on its own stream and at a
     different episode phase, advance together and end bit-identical to the same scans iterated
