@@ -40,3 +40,49 @@ def test_volume_at_matches_literal_volume():
     got = D.volume_at(po, theta, pts)
     ref = vol[pts[:, 0], pts[:, 1], pts[:, 2]]
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(vol).max()
+
+
+def test_bilinear_weights_partition_unity_and_centroid():
+    """Each sample's four weights sum to 1 and their weighted cell position is the sample's
+    real position (bilinear interpolation reproduces linear functions)."""
+    import math
+    N, Np = 32, 7
+    theta = np.pi * np.arange(Np) / Np
+    iy, ix, w = D.bilinear_cells(N, theta)
+    assert np.all(w >= 0) and np.allclose(w.sum(-1), 1.0, atol=1e-14)
+    for n in range(Np):
+        for iu in range(N):
+            u = iu - N // 2
+            x, y = -(u * math.sin(theta[n])), u * math.cos(theta[n])
+            # unwrap the centred indices next to the sample before averaging
+            cx = (ix[n, iu] - N // 2 - math.floor(x) + N // 2) % N - N // 2 + math.floor(x)
+            cy = (iy[n, iu] - N // 2 - math.floor(y) + N // 2) % N - N // 2 + math.floor(y)
+            assert abs(np.dot(w[n, iu], cx) - x) < 1e-12 and abs(np.dot(w[n, iu], cy) - y) < 1e-12
+
+
+def test_bilinear_equals_nearest_on_axis_angles_and_averages_constants():
+    """At theta = 0 every sample sits on a cell (weights 0/1), so bilinear insertion equals the
+    nearest-voxel one; a constant spectrum inserts as that constant on every touched cell."""
+    rng = np.random.default_rng(3)
+    N = 16
+    E = rng.standard_normal((1, N, N)) + 1j * rng.standard_normal((1, N, N))
+    th = np.array([0.0])
+    assert np.allclose(D.insert_slices(E, th, "bilinear"), D.insert_slices(E, th, "nearest"), atol=1e-15)
+    th = np.pi * np.arange(5) / 5
+    ones = np.ones((5, N, N), complex)
+    g = D.insert_slices(ones, th, "bilinear")
+    iy, ix, w = D.bilinear_cells(N, th)
+    touched = np.zeros((N, N), bool)
+    touched[iy[w > 0], ix[w > 0]] = True
+    assert np.allclose(g[:, touched], 1.0, atol=1e-12) and np.all(g[:, ~touched] == 0)
+
+
+def test_bilinear_volume_at_matches_literal_grid():
+    rng = np.random.default_rng(4)
+    N, Np = 16, 5
+    obj = rng.standard_normal((Np, N, N))
+    th = np.pi * np.arange(Np) / Np
+    vol = D.assemble_volume(obj, th, "bilinear")
+    pts = rng.integers(0, N, size=(20, 3))
+    got = D.volume_at(obj, th, pts, "bilinear")
+    assert np.allclose(got, vol[pts[:, 0], pts[:, 1], pts[:, 2]], atol=1e-12 * np.abs(vol).max())
