@@ -46,6 +46,7 @@ typedef enum {
 } cpra_status;
 
 enum { CPRA_HIO = 0, CPRA_ER = 1, CPRA_RAAR = 2 };   /* real-space update     */
+enum { CPRA_INSERT_NEAREST = 0, CPRA_INSERT_BILINEAR = 1 };   /* step D insertion */
 enum { CPRA_WRAP_MIRROR = 0, CPRA_WRAP_PLAIN = 1 };  /* carousel seam rule    */
 enum { CPRA_REAL_F32 = 0, CPRA_REAL_F64 = 1 };       /* arithmetic precision  */
 enum { CPRA_AMP_F32 = 0, CPRA_AMP_F16 = 1 };         /* amplitude storage     */
@@ -69,6 +70,9 @@ typedef struct {
                             (step C's random guesses; 0 means 1).  Guess r of angle n is
                             slot r * Np + n: its own iterate and random start (phase
                             stream index r * Np + n), the angle's data shared.        */
+  int32_t insertion;     /* step D's interpolation: CPRA_INSERT_NEAREST (nearest voxel,
+                            plain average) or CPRA_INSERT_BILINEAR (four cells around the
+                            slice point, weighted average sum(w E) / sum(w))          */
 } cpra_params;
 
 /*
@@ -209,7 +213,9 @@ cpra_status cpra_load_objects(cpra_plan_t plan, const void* objects, int32_t ptr
 /*
  * Step D: insert the spectra F2(O'_n) of the current estimates along their
  * Fourier slices (nearest voxel of (-u sin t, u cos t, w), floor(x+0.5) in
- * FP64, averaged per voxel, empty voxels zero) and return the real part of
+ * FP64, averaged per voxel; or, with CPRA_INSERT_BILINEAR, the four voxels
+ * around that point with bilinear weights built in FP64, weighted average;
+ * empty voxels zero) and return the real part of
  * the 3D inverse transform: N x N x N [z][y][x] centred, float (F32 plans)
  * or double (F64 plans), device memory.  Computed z-plane by z-plane (the
  * 3D transform factorises into the row spectra already held per angle), so

@@ -3,6 +3,6 @@
 The Python layer only marshals arguments; see include/cpra.h for the ABI.
 """
 from ._lib import (  # noqa: F401
-    AMP_F16, AMP_F32, ER, HIO, RAAR, REAL_F32, REAL_F64, WRAP_MIRROR, WRAP_PLAIN, CpraError, Plan, coupling_table,
-    iterate_batch, load, make_params, slice_cells, workspace_size,
+    AMP_F16, AMP_F32, ER, HIO, INSERT_BILINEAR, INSERT_NEAREST, RAAR, REAL_F32, REAL_F64, WRAP_MIRROR,
+    WRAP_PLAIN, CpraError, Plan, coupling_table, iterate_batch, load, make_params, slice_cells, workspace_size,
 )

@@ -19,6 +19,7 @@ CPRA_OK = 0
 STATUS = {0: "OK", -1: "ERR_ARG", -2: "ERR_OOM", -3: "ERR_DEVICE", -4: "ERR_STATE", -5: "ERR_UNSUPPORTED",
           -6: "ERR_DATA"}
 HIO, ER, RAAR = 0, 1, 2
+INSERT_NEAREST, INSERT_BILINEAR = 0, 1
 WRAP_MIRROR, WRAP_PLAIN = 0, 1
 REAL_F32, REAL_F64 = 0, 1
 AMP_F32, AMP_F16 = 0, 1
@@ -46,6 +47,7 @@ class Params(ctypes.Structure):
         ("amp_type", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("n_guess", ctypes.c_int32),
+        ("insertion", ctypes.c_int32),
     ]
 
 
@@ -110,7 +112,7 @@ def iterate_batch(plans, n_iter, algo=HIO, beta=0.9):
 
 
 def make_params(N, Np, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=WRAP_MIRROR, positivity=True,
-                real=REAL_F32, amp=AMP_F32, seed=0, n_guess=1):
+                real=REAL_F32, amp=AMP_F32, seed=0, n_guess=1, insertion=0):
     p = Params()
     p.struct_size = ctypes.sizeof(Params)
     p.N, p.Np = int(N), int(Np)
@@ -125,6 +127,7 @@ def make_params(N, Np, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=WRAP_MIR
     p.real_type, p.amp_type = int(real), int(amp)
     p.seed = int(seed) % (1 << 64)
     p.n_guess = int(n_guess)
+    p.insertion = int(insertion)
     return p
 
 
@@ -158,11 +161,11 @@ class Plan:
     """One scan on the current device: owns a torch workspace tensor and a library plan."""
 
     def __init__(self, N, Np, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=WRAP_MIRROR, positivity=True,
-                 real=REAL_F32, amp=AMP_F32, seed=0, stream=None, device=None, n_guess=1):
+                 real=REAL_F32, amp=AMP_F32, seed=0, stream=None, device=None, n_guess=1, insertion=0):
         import torch
         self.torch = torch
         lib = load()
-        self.params = make_params(N, Np, theta, alpha, n_ei, wrap, positivity, real, amp, seed, n_guess)
+        self.params = make_params(N, Np, theta, alpha, n_ei, wrap, positivity, real, amp, seed, n_guess, insertion)
         self.N, self.Np = int(N), int(Np)
         self.R = max(1, int(n_guess))
         self.real = real

@@ -64,6 +64,9 @@ cpra_status validate(const cpra_params* p, std::string& msg) {
   if (p->struct_size != sizeof(cpra_params)) { msg = "params.struct_size mismatch"; return CPRA_ERR_ARG; }
   if (!size_supported(p->N)) { msg = "N must be 64, 128, 256, 512 or 1024"; return CPRA_ERR_UNSUPPORTED; }
   if (p->Np < 1) { msg = "Np must be >= 1"; return CPRA_ERR_ARG; }
+  if (p->insertion != CPRA_INSERT_NEAREST && p->insertion != CPRA_INSERT_BILINEAR) {
+    msg = "bad insertion"; return CPRA_ERR_ARG;
+  }
   if (p->n_guess < 0 || (int64_t)p->Np * std::max(1, p->n_guess) > (1 << 24)) {
     msg = "n_guess must be >= 0 (0 = one) with n_guess * Np <= 2^24"; return CPRA_ERR_ARG;
   }
@@ -114,7 +117,9 @@ Layout layout_of(const cpra_params* p) {
   L.stage_I = take((size_t)kStageAngles * N * N * 4);
   L.stage_S = take((size_t)kStageAngles * N * N);
   L.csr_ptr = take((N * N + 1) * 4);
-  L.csr_ent = take(Np * N * 4);
+  const size_t ents = Np * N * (p->insertion == CPRA_INSERT_BILINEAR ? 4 : 1);   // at most
+  L.csr_ent = take(ents * 4);
+  L.csr_w = take(p->insertion == CPRA_INSERT_BILINEAR ? ents * rs : 0);
   L.cnt_inv = take(N * N * rs);
   L.zc = stepd_chunk(p->N);
   L.plane = take((size_t)L.zc * N * N * cs);
@@ -237,15 +242,26 @@ cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t 
   if (e == hipSuccess) e = hipMemsetAsync(pl->ws + L.flags, 0, 256, pl->stream);
   // step-D tables (integer map built on the host in FP64)
   std::vector<int32_t> rp, ent;
-  cpra_host::insertion_csr(params->N, params->Np, pl->theta.data(), rp, ent);
+  std::vector<double> wts;
+  const bool bil = params->insertion == CPRA_INSERT_BILINEAR;
+  if (bil) cpra_host::insertion_csr_bilinear(params->N, params->Np, pl->theta.data(), rp, ent, wts);
+  else cpra_host::insertion_csr(params->N, params->Np, pl->theta.data(), rp, ent);
   const size_t NN = (size_t)params->N * params->N;
   if (e == hipSuccess) e = hipMemcpyAsync(pl->ws + L.csr_ptr, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, pl->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(pl->ws + L.csr_ent, ent.data(), ent.size() * 4, hipMemcpyHostToDevice, pl->stream);
+  std::vector<float> wts_f(wts.begin(), wts.end());
+  if (bil && e == hipSuccess) {
+    if (params->real_type == CPRA_REAL_F64)
+      e = hipMemcpyAsync(pl->ws + L.csr_w, wts.data(), wts.size() * 8, hipMemcpyHostToDevice, pl->stream);
+    else
+      e = hipMemcpyAsync(pl->ws + L.csr_w, wts_f.data(), wts_f.size() * 4, hipMemcpyHostToDevice, pl->stream);
+  }
   std::vector<double> inv_d(NN);
   std::vector<float> inv_f(NN);
   for (size_t c = 0; c < NN; ++c) {
-    int cnt = rp[c + 1] - rp[c];
-    inv_d[c] = cnt ? 1.0 / cnt : 0.0;
+    double tot = 0.0;   // entry count, or the sum of the bilinear weights (in entry order)
+    for (int i = rp[c]; i < rp[c + 1]; ++i) tot += bil ? wts[i] : 1.0;
+    inv_d[c] = tot > 0.0 ? 1.0 / tot : 0.0;
     inv_f[c] = (float)inv_d[c];
   }
   if (e == hipSuccess) {

@@ -51,6 +51,48 @@ void insertion_csr(int N, int Np, const double* theta, std::vector<int32_t>& row
   }
 }
 
+// Bilinear insertion: sample (n, u) at (x, y) = (-u sin t, u cos t) spreads over the four cells
+// around it with weights (1-fy)(1-fx), (1-fy)fx, fy(1-fx), fy fx (fx = x - floor x, fy = y -
+// floor y); entries with weight exactly 0 are left out.  Same CSR layout as insertion_csr, plus
+// the weight of every entry.
+void insertion_csr_bilinear(int N, int Np, const double* theta, std::vector<int32_t>& row_ptr,
+                            std::vector<int32_t>& entries, std::vector<double>& weights) {
+  struct Hit { int32_t cell, code; double w; };
+  std::vector<Hit> hits;
+  hits.reserve((size_t)Np * N * 4);
+  for (int n = 0; n < Np; ++n) {
+    const double t = theta ? theta[n] : default_theta(n, Np);
+    const double s = std::sin(t), c = std::cos(t);
+    for (int iu = 0; iu < N; ++iu) {
+      const double u = (double)(iu - N / 2);
+      const double x = -(u * s);
+      const double y = u * c;
+      const double x0 = std::floor(x), y0 = std::floor(y);
+      const double fx = x - x0, fy = y - y0;
+      const long cx[4] = {(long)x0, (long)x0 + 1, (long)x0, (long)x0 + 1};
+      const long cy[4] = {(long)y0, (long)y0, (long)y0 + 1, (long)y0 + 1};
+      const double w[4] = {(1.0 - fy) * (1.0 - fx), (1.0 - fy) * fx, fy * (1.0 - fx), fy * fx};
+      const int un = ((iu - N / 2) % N + N) % N;
+      for (int k = 0; k < 4; ++k) {
+        if (w[k] == 0.0) continue;
+        const long kx = ((cx[k] % N) + N) % N, ky = ((cy[k] % N) + N) % N;
+        hits.push_back(Hit{(int32_t)(ky * N + kx), n * N + un, w[k]});
+      }
+    }
+  }
+  row_ptr.assign((size_t)N * N + 1, 0);
+  for (const Hit& h : hits) row_ptr[(size_t)h.cell + 1]++;
+  for (size_t c = 0; c < (size_t)N * N; ++c) row_ptr[c + 1] += row_ptr[c];
+  entries.assign(hits.size(), 0);
+  weights.assign(hits.size(), 0.0);
+  std::vector<int32_t> fill(row_ptr.begin(), row_ptr.end() - 1);
+  for (const Hit& h : hits) {
+    const int32_t at = fill[h.cell]++;
+    entries[at] = h.code;
+    weights[at] = h.w;
+  }
+}
+
 void coupling_table(int Np, const uint8_t* present, const double alpha[3], int wrap_mirror,
                     std::vector<Coupling>& out) {
   out.assign(Np, Coupling{});

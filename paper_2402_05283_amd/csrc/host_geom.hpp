@@ -16,6 +16,8 @@ double default_theta(int n, int Np);
 void slice_cells(int N, int Np, const double* theta, int32_t* kx, int32_t* ky);
 void insertion_csr(int N, int Np, const double* theta, std::vector<int32_t>& row_ptr,
                    std::vector<int32_t>& entries);
+void insertion_csr_bilinear(int N, int Np, const double* theta, std::vector<int32_t>& row_ptr,
+                            std::vector<int32_t>& entries, std::vector<double>& weights);
 void coupling_table(int Np, const uint8_t* present, const double alpha[3], int wrap_mirror,
                     std::vector<Coupling>& out);
 

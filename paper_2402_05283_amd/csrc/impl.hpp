@@ -15,7 +15,7 @@ namespace cpra_impl {
 
 struct Layout {
   size_t P, Pmid, g0, g1, A2, ampscale, maskw, den, tw, coup, alist, errpart, errhist, flags, stage_I,
-      stage_S, csr_ptr, csr_ent, cnt_inv, plane, prep_part, mtab, total;
+      stage_S, csr_ptr, csr_ent, csr_w, cnt_inv, plane, prep_part, mtab, total;
   int zc;   // z-planes per step-D chunk
 };
 
@@ -188,6 +188,7 @@ struct Impl {
   }
   static void assemble(cpra_plan_t pl, void* vol) {
     stepd_run<N, T>(at<C>(pl, pl->L.P), at<int>(pl, pl->L.csr_ptr), at<int>(pl, pl->L.csr_ent),
+                    pl->p.insertion == CPRA_INSERT_BILINEAR ? at<T>(pl, pl->L.csr_w) : nullptr,
                     at<T>(pl, pl->L.cnt_inv), at<C>(pl, pl->L.tw), at<C>(pl, pl->L.plane), pl->L.zc,
                     reinterpret_cast<T*>(vol), pl->stream);
   }

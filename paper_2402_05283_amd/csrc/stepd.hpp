@@ -39,7 +39,8 @@ __device__ __forceinline__ cx<T> spectrum_at(const cx<T>* Pn, int z, int u) {
 template <int N, typename T, int RB>
 __global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
     k_stepd_rows(const cx<T>* __restrict__ P, const int* __restrict__ ptr, const int* __restrict__ ent,
-                 const T* __restrict__ cnt_inv, const cx<T>* __restrict__ tw, cx<T>* __restrict__ plane, int z0) {
+                 const T* __restrict__ wts, const T* __restrict__ cnt_inv, const cx<T>* __restrict__ tw,
+                 cx<T>* __restrict__ plane, int z0) {
   using C = cx<T>;
   constexpr int R1 = StepdCfg<N>::R1, R2 = StepdCfg<N>::R2, Q = R2 / R1, H = N / 2;
   static_assert(R1 * R2 == N && Q >= 1 && R2 % R1 == 0, "step D decomposition");
@@ -63,6 +64,7 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
       const int n = code / N, u = code % N;
       C s = spectrum_at<N, T>(P + (size_t)n * N * H, z, u);
       if (u & 1) { s.x = -s.x; s.y = -s.y; }
+      if (wts) s = cscale(s, wts[e]);      // bilinear insertion weight
       acc = cadd(acc, s);
     }
     T f = cnt_inv[cell];
@@ -125,14 +127,14 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* CC)
 
 // tw: W_N^j, j < N (the first N entries of the plan's twiddle table)
 template <int N, typename T>
-void stepd_run(const cx<T>* P, const int* ptr, const int* ent, const T* cnt_inv, const cx<T>* tw, cx<T>* plane,
-               int zc, T* vol, hipStream_t st) {
+void stepd_run(const cx<T>* P, const int* ptr, const int* ent, const T* wts, const T* cnt_inv, const cx<T>* tw,
+               cx<T>* plane, int zc, T* vol, hipStream_t st) {
   constexpr int R1 = StepdCfg<N>::R1;
   constexpr int RB = (256 / R1) < N ? (256 / R1) : N;
   constexpr int CC = (256 / R1) < N ? (256 / R1) : N;
   for (int z0 = 0; z0 < N; z0 += zc) {
     const int nz = (N - z0) < zc ? (N - z0) : zc;
-    k_stepd_rows<N, T, RB><<<dim3(N / RB, nz), R1 * RB, 0, st>>>(P, ptr, ent, cnt_inv, tw, plane, z0);
+    k_stepd_rows<N, T, RB><<<dim3(N / RB, nz), R1 * RB, 0, st>>>(P, ptr, ent, wts, cnt_inv, tw, plane, z0);
     k_stepd_cols<N, T, CC><<<dim3(N / CC, nz), R1 * CC, 0, st>>>(plane, tw, vol, z0);
   }
 }

@@ -40,7 +40,8 @@ def test_workspace_size_and_validation():
     bad = [
         dict(N=100, Np=4), dict(N=64, Np=0), dict(N=64, Np=4, n_ei=0), dict(N=64, Np=4, alpha=(0.5, 0.6, 0.2)),
         dict(N=64, Np=4, alpha=(-0.1, 1.0, 0.1)), dict(N=64, Np=4, real=cp.REAL_F64, amp=cp.AMP_F16),
-        dict(N=64, Np=4, wrap=7), dict(N=64, Np=4, theta=[0.0, np.nan, 1.0, 2.0]),
+        dict(N=64, Np=4, wrap=7), dict(N=64, Np=4, theta=[0.0, np.nan, 1.0, 2.0]), dict(N=64, Np=4, insertion=2),
+        dict(N=64, Np=4, n_guess=-1),
     ]
     for kw in bad:
         with pytest.raises(cp.CpraError) as e:

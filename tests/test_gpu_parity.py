@@ -236,6 +236,34 @@ def test_step_d_sampled_voxels(torch, N, Np, real):
     assert np.abs(got - ref).max() <= tol * scale
 
 
+@pytest.mark.parametrize("real", [F32, F64])
+@pytest.mark.parametrize("N,Np", [(64, 16), (512, 5)])
+def test_step_d_bilinear(torch, N, Np, real):
+    """Bilinear insertion (four cells per slice point, weighted average): the whole volume at
+    N = 64 against the oracle's literal grid, sampled voxels at N = 512."""
+    import paper_2402_05283_amd as cp
+    from oracle import stepd as D
+    scan = make_scan(1, N=N, Np=Np)
+    banner(f"step D bilinear N={N} real={real}")
+    plan = cp.Plan(N, Np, theta=scan["theta"], n_ei=1, real=real, seed=scan["phase_seed"],
+                   insertion=cp.INSERT_BILINEAR)
+    plan.submit(0, torch.from_numpy(scan["I"]).cuda(), torch.from_numpy(scan["support"]).cuda())
+    plan.iterate(1, cp.HIO, 0.9)
+    vol = plan.assemble_volume()
+    torch.cuda.synchronize()
+    o, _ = run_oracle(scan, [(1, HIO, 0.9)], n_ei=1)
+    tol = 1e-5 if real == F32 else 1e-11
+    if N == 64:
+        assert rel_l2(vol.cpu().numpy(), D.assemble_volume(o.g, scan["theta"], "bilinear")) <= tol
+    else:
+        rng = np.random.default_rng(N + 1)
+        pts = np.concatenate([rng.integers(N // 4, 3 * N // 4, size=(24, 3)), np.array([[N // 2] * 3])])
+        idx = torch.from_numpy(pts).long().cuda()
+        got = vol[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+        ref = D.volume_at(o.g, scan["theta"], pts, "bilinear")
+        assert np.abs(got - ref).max() <= (1e-4 if real == F32 else 1e-10) * np.abs(ref).max()
+
+
 def test_deterministic_and_homogeneous(torch):
     """Same inputs give bitwise-equal results; scaling I by 4 scales every iterate by exactly 2."""
     scan = make_scan(1, Np=6)
