@@ -110,6 +110,29 @@ def real_space_update(g, gp, support, algo, beta, positivity, estimate):
     raise ValueError("algo must be HIO, ER or RAAR")
 
 
+def gaussian_window(sigma: float) -> np.ndarray:
+    """Sampled 1D Gaussian exp(-d^2 / (2 sigma^2)), d = -W..W with W = ceil(4 sigma), normalised
+    to sum 1 (the window of the shrinkwrap blur)."""
+    W = int(np.ceil(4.0 * sigma))
+    d = np.arange(-W, W + 1, dtype=np.float64)
+    k = np.exp(-d * d / (2.0 * sigma * sigma))
+    return k / k.sum()
+
+
+def shrinkwrap_support(g: np.ndarray, sigma: float, threshold: float) -> np.ndarray:
+    """Shrinkwrap support update (the conventional 2D shrinkwrap step the paper runs at the end
+    of each episode): blur the object with the periodic 2D Gaussian K(dz, dt) = k(dz) k(dt) of
+    gaussian_window, b[z][t] = sum K(dz, dt) g[z - dz][t - dt] (indices mod N), and keep the pixels
+    where b >= threshold * max(b)."""
+    k = gaussian_window(sigma)
+    W = (len(k) - 1) // 2
+    b = np.zeros_like(g, dtype=np.float64)
+    for dz in range(-W, W + 1):
+        for dt in range(-W, W + 1):
+            b += k[dz + W] * k[dt + W] * np.roll(g, (dz, dt), axis=(0, 1))
+    return b >= threshold * b.max()
+
+
 def coupling_weights(Np, present, alpha, wrap):
     """Per angle: ((left, w_left, mirror_left), w_self, (right, w_right, mirror_right)).
 
@@ -205,6 +228,11 @@ class Oracle:
                 self.g[n] = real_space_update(self.g[n], gp, self.S[n], algo, beta, self.positivity, estimate)
             self.k += 1
         return err
+
+    def shrinkwrap(self, sigma, threshold):
+        """Replace the support of every present angle by the shrinkwrap of its current object."""
+        for n in np.flatnonzero(self.present):
+            self.S[n] = shrinkwrap_support(self.g[n], sigma, threshold)
 
     def objects(self):
         return self.g.copy()

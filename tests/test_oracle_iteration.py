@@ -150,3 +150,30 @@ def test_true_object_is_fixed_point_of_raar(scan_c1):
     o = _oracle_with_state(po, A, S)
     o.iterate(3, C.RAAR, 0.9)
     assert np.abs(o.g - po).max() <= 1e-12 * po.max()
+
+
+def test_shrinkwrap_window_and_delta_closed_form():
+    """A delta at (z0, t0) blurs to k(z - z0) k(t - t0), so the support kept at a fraction f of the
+    maximum is the disc exp(-r^2 / 2 sigma^2) >= f (periodic distance r, inside the window)."""
+    k = C.gaussian_window(1.5)
+    assert len(k) == 2 * 6 + 1 and abs(k.sum() - 1) < 1e-15 and np.all(np.diff(k[:7]) > 0)
+    N, sigma, f = 32, 2.0, 0.3
+    g = np.zeros((N, N))
+    g[1, N - 2] = 5.0                                  # near a corner: the blur wraps
+    S = C.shrinkwrap_support(g, sigma, f)
+    dz = np.minimum(np.abs(np.arange(N) - 1), N - np.abs(np.arange(N) - 1))
+    dt = np.minimum(np.abs(np.arange(N) - (N - 2)), N - np.abs(np.arange(N) - (N - 2)))
+    r2 = dz[:, None] ** 2 + dt[None, :] ** 2
+    inside = (dz[:, None] <= 8) & (dt[None, :] <= 8)
+    want = inside & (np.exp(-r2 / (2 * sigma ** 2)) >= f - 1e-12)
+    assert np.array_equal(S, want)
+
+
+def test_shrinkwrap_small_sigma_is_a_plain_threshold():
+    """sigma -> 0: the window is a single tap, the blur is the identity."""
+    rng = np.random.default_rng(6)
+    g = rng.uniform(size=(16, 16))
+    assert len(C.gaussian_window(0.2)) == 3
+    k = C.gaussian_window(0.05)
+    assert k[1] == 1.0 and k[0] < 1e-80
+    assert np.array_equal(C.shrinkwrap_support(g, 0.05, 0.5), g >= 0.5 * g.max())
