@@ -191,6 +191,25 @@ cpra_status cpra_merge(cpra_plan_t plan, int32_t n_best, int32_t* kept, int32_t*
 cpra_status cpra_iterate_batch(cpra_plan_t* plans, int32_t count, int32_t n_iter, int32_t algo, double beta);
 
 /*
+ * Shrinkwrap support update (the conventional 2D shrinkwrap step, run by
+ * the paper at the end of each episode to tighten the space constraints):
+ * for every present angle, blur the current object with the periodic 2D
+ * Gaussian k(dz) k(dt), k(d) = exp(-d^2 / 2 sigma^2) for |d| <= ceil(4
+ * sigma) normalised to sum 1, and make the support the pixels where the
+ * blurred object is >= threshold * its maximum.  Replaces the submitted
+ * supports.  ERR_ARG unless sigma > 0 with ceil(4 sigma) < N/2 and
+ * 0 < threshold <= 1; ERR_UNSUPPORTED for plans with several guesses (the
+ * support is per angle); ERR_STATE unless k mod n_ei == 0.  Synchronises.
+ */
+cpra_status cpra_shrinkwrap(cpra_plan_t plan, double sigma, double threshold);
+
+/*
+ * The supports in use, Np x N x N [n][z][t] centred, 0/1 bytes, into host
+ * memory (as submitted, or as replaced by cpra_shrinkwrap).  Synchronises.
+ */
+cpra_status cpra_read_support(cpra_plan_t plan, uint8_t* out);
+
+/*
  * Current real-space iterate of every slot, n_guess x Np x N x N [r][n][z][t]
  * centred, float (F32 plans) or double (F64 plans), host or device.  At an
  * episode end this is the episode's estimate.  Host copies synchronise the

@@ -124,13 +124,19 @@ def shrinkwrap_support(g: np.ndarray, sigma: float, threshold: float) -> np.ndar
     of each episode): blur the object with the periodic 2D Gaussian K(dz, dt) = k(dz) k(dt) of
     gaussian_window, b[z][t] = sum K(dz, dt) g[z - dz][t - dt] (indices mod N), and keep the pixels
     where b >= threshold * max(b)."""
+    b = shrinkwrap_blur(g, sigma)
+    return b >= threshold * b.max()
+
+
+def shrinkwrap_blur(g: np.ndarray, sigma: float) -> np.ndarray:
+    """b[z][t] = sum_{dz, dt} k(dz) k(dt) g[z - dz][t - dt], indices mod N."""
     k = gaussian_window(sigma)
     W = (len(k) - 1) // 2
     b = np.zeros_like(g, dtype=np.float64)
     for dz in range(-W, W + 1):
         for dt in range(-W, W + 1):
             b += k[dz + W] * k[dt + W] * np.roll(g, (dz, dt), axis=(0, 1))
-    return b >= threshold * b.max()
+    return b
 
 
 def coupling_weights(Np, present, alpha, wrap):

@@ -29,7 +29,8 @@ EXPORTED = [
     "cpra_workspace_size", "cpra_plan_create", "cpra_submit_angles", "cpra_iterate", "cpra_read_objects",
     "cpra_assemble_volume", "cpra_destroy", "cpra_last_error", "cpra_iteration_count", "cpra_slice_cells",
     "cpra_coupling_table", "cpra_set_kernel_timing", "cpra_kernel_timing", "cpra_load_objects",
-    "cpra_iterate_batch", "cpra_prereconstruct", "cpra_sweep", "cpra_merge",
+    "cpra_iterate_batch", "cpra_prereconstruct", "cpra_sweep", "cpra_merge", "cpra_shrinkwrap",
+    "cpra_read_support",
 ]
 
 
@@ -81,6 +82,8 @@ def load():
     lib.cpra_prereconstruct.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_double, c.c_void_p]
     lib.cpra_sweep.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_double, c.c_void_p]
     lib.cpra_merge.argtypes = [c.c_void_p, c.c_int32, c.c_void_p, c.c_void_p]
+    lib.cpra_shrinkwrap.argtypes = [c.c_void_p, c.c_double, c.c_double]
+    lib.cpra_read_support.argtypes = [c.c_void_p, c.c_void_p]
     lib.cpra_last_error.argtypes = [c.c_void_p]
     lib.cpra_last_error.restype = c.c_char_p
     lib.cpra_iteration_count.argtypes = [c.c_void_p, P(c.c_int64)]
@@ -254,6 +257,16 @@ class Plan:
         inv = np.zeros(n_best, np.int32)
         _check(load().cpra_merge(self.handle, int(n_best), kept.ctypes.data, inv.ctypes.data), self.handle)
         return kept, inv.astype(bool)
+
+    def shrinkwrap(self, sigma, threshold):
+        """Replace every present angle's support by the shrinkwrap of its current object."""
+        _check(load().cpra_shrinkwrap(self.handle, float(sigma), float(threshold)), self.handle)
+
+    def support(self):
+        """The supports in use, (Np, N, N) uint8 (host)."""
+        out = np.zeros((self.Np, self.N, self.N), np.uint8)
+        _check(load().cpra_read_support(self.handle, out.ctypes.data), self.handle)
+        return out
 
     def objects(self, out=None):
         """Current iterates: (Np, N, N), or (n_guess, Np, N, N) for several guesses."""

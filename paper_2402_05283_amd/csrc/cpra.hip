@@ -59,6 +59,26 @@ size_t mask_words_per_row(int N) {
   }
 }
 
+int tau_count(int N) {
+  switch (N) {
+    case 64: return RowGeom<64>::T;
+    case 128: return RowGeom<128>::T;
+    case 256: return RowGeom<256>::T;
+    case 512: return RowGeom<512>::T;
+    default: return RowGeom<1024>::T;
+  }
+}
+
+int bit_to_t(int N, int tau, int b) {
+  switch (N) {
+    case 64: return mask_bit_t<64>(tau, b);
+    case 128: return mask_bit_t<128>(tau, b);
+    case 256: return mask_bit_t<256>(tau, b);
+    case 512: return mask_bit_t<512>(tau, b);
+    default: return mask_bit_t<1024>(tau, b);
+  }
+}
+
 cpra_status validate(const cpra_params* p, std::string& msg) {
   if (!p) { msg = "params is NULL"; return CPRA_ERR_ARG; }
   if (p->struct_size != sizeof(cpra_params)) { msg = "params.struct_size mismatch"; return CPRA_ERR_ARG; }
@@ -125,6 +145,7 @@ Layout layout_of(const cpra_params* p) {
   L.plane = take((size_t)L.zc * N * N * cs);
   L.prep_part = take(Np * cpra::kPrepBlocks * 12);
   L.mtab = take(S * 3 * 8 + S * 4 * 4 + (S / Np) * 64 + 256);   // step C tables
+  L.swk = take((N + 1) * rs);                                      // shrinkwrap window taps
   L.total = o;
   return L;
 }
@@ -651,6 +672,63 @@ cpra_status cpra_merge(cpra_plan_t pl, int32_t n_best, int32_t* kept, int32_t* i
   pl->tables_dirty = true;
   if (kept) std::copy(keep.begin(), keep.end(), kept);
   if (inverted) std::copy(inv.begin(), inv.end(), inverted);
+  return CPRA_OK;
+}
+
+cpra_status cpra_shrinkwrap(cpra_plan_t pl, double sigma, double threshold) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
+  const int N = pl->p.N, Np = pl->p.Np;
+  if (!(sigma > 0.0) || !(4.0 * sigma <= N / 2 - 1))
+    return fail(pl, CPRA_ERR_ARG, "sigma must be > 0 with ceil(4 sigma) < N/2");
+  if (!(threshold > 0.0 && threshold <= 1.0)) return fail(pl, CPRA_ERR_ARG, "threshold must be in (0, 1]");
+  if (pl->R != 1) return fail(pl, CPRA_ERR_UNSUPPORTED, "shrinkwrap needs a one-guess plan (supports are per angle)");
+  if (pl->k % pl->p.n_ei != 0)
+    return fail(pl, CPRA_ERR_STATE, "shrinkwrap needs an episode end (k=%lld)", (long long)pl->k);
+  std::vector<int32_t> ids;
+  for (int n = 0; n < Np; ++n)
+    if (pl->present[n]) ids.push_back(n);
+  if (ids.empty()) return fail(pl, CPRA_ERR_STATE, "no angle is present");
+  // window taps exp(-d^2 / 2 sigma^2), d = -W..W, W = ceil(4 sigma), normalised in FP64
+  const int W = (int)std::ceil(4.0 * sigma);
+  std::vector<double> k(2 * W + 1);
+  double ks = 0.0;
+  for (int d = -W; d <= W; ++d) ks += (k[d + W] = std::exp(-(double)d * d / (2.0 * sigma * sigma)));
+  for (double& v : k) v /= ks;
+  std::vector<float> kf(k.begin(), k.end());
+  const bool f64 = pl->p.real_type == CPRA_REAL_F64;
+  HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.swk, f64 ? (const void*)k.data() : (const void*)kf.data(),
+                            k.size() * (f64 ? 8 : 4), hipMemcpyHostToDevice, pl->stream));
+  HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, pl->stream));
+  Ops ops = ops_of(pl->p);
+  ops.shrinkwrap(pl, at<int>(pl, pl->L.alist), (int)ids.size(), W, threshold);
+  LAUNCHCHK(pl);
+  HIPCHK(pl, hipStreamSynchronize(pl->stream));   // host vectors go out of scope
+  pl->tables_dirty = true;                         // alist was used as scratch
+  return CPRA_OK;
+}
+
+cpra_status cpra_read_support(cpra_plan_t pl, uint8_t* out) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
+  if (!out) return fail(pl, CPRA_ERR_ARG, "out is NULL");
+  const int N = pl->p.N, Np = pl->p.Np;
+  const size_t wpr = mask_words_per_row(N);          // words per row, in the row pass's thread order
+  std::vector<uint32_t> w((size_t)Np * N * wpr);
+  HIPCHK(pl, hipMemcpyAsync(w.data(), pl->ws + pl->L.maskw, w.size() * 4, hipMemcpyDeviceToHost, pl->stream));
+  HIPCHK(pl, hipStreamSynchronize(pl->stream));
+  const int mw = (int)(wpr / tau_count(N));
+  std::fill(out, out + (size_t)Np * N * N, (uint8_t)0);
+  for (int n = 0; n < Np; ++n)
+    for (int z = 0; z < N; ++z)
+      for (size_t r = 0; r < wpr; ++r) {
+        const uint32_t word = w[((size_t)n * N + z) * wpr + r];
+        const int tau = (int)r / mw, wd = (int)r % mw;
+        for (int b = 0; b < 32; ++b) {
+          const int t = bit_to_t(N, tau, wd * 32 + b);
+          if (t >= 0 && ((word >> b) & 1u)) out[((size_t)n * N + z) * N + t] = 1;
+        }
+      }
   return CPRA_OK;
 }
 

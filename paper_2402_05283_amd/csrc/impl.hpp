@@ -9,13 +9,14 @@
 #include "host_geom.hpp"
 #include "kernels.hpp"
 #include "merge.hpp"
+#include "shrink.hpp"
 #include "stepd.hpp"
 
 namespace cpra_impl {
 
 struct Layout {
   size_t P, Pmid, g0, g1, A2, ampscale, maskw, den, tw, coup, alist, errpart, errhist, flags, stage_I,
-      stage_S, csr_ptr, csr_ent, csr_w, cnt_inv, plane, prep_part, mtab, total;
+      stage_S, csr_ptr, csr_ent, csr_w, cnt_inv, plane, prep_part, mtab, swk, total;
   int zc;   // z-planes per step-D chunk
 };
 
@@ -72,6 +73,7 @@ struct Ops {
   void (*moments)(cpra_plan_t, const int*, int, double*);
   void (*twin)(cpra_plan_t, const int*, const int*, int, double*);
   void (*merge_avg)(cpra_plan_t, int, const int*, const int*, const int*, void*);
+  void (*shrinkwrap)(cpra_plan_t, const int*, int, int, double);
 };
 
 template <int N, typename T, typename AP>
@@ -186,6 +188,18 @@ struct Impl {
                                           at<C>(pl, pl->L.tw), d_list, nullptr, pl->p.Np, 3, (T)0,
                                           pl->p.positivity);
   }
+  // support of the listed slots (one guess: slot = data angle) from their current objects; the
+  // blurred planes use the Pmid scratch, the window taps sit at L.swk, partial maxima at errpart
+  static void shrinkwrap(cpra_plan_t pl, const int* list, int count, int W, double frac) {
+    constexpr int CB = 8;
+    T* buf = at<T>(pl, pl->L.Pmid);
+    double* pm = at<double>(pl, pl->L.errpart);
+    k_blur_rows<N, T><<<dim3(N, count), 256, 0, pl->stream>>>(at<T>(pl, pl->cur ? pl->L.g1 : pl->L.g0), list,
+                                                              at<T>(pl, pl->L.swk), W, buf);
+    k_blur_cols<N, T, CB><<<dim3(N / CB, count), 256, 0, pl->stream>>>(buf, at<T>(pl, pl->L.swk), W, pm);
+    k_shrink_mask<N, T, CB><<<dim3(N, count), 256, 0, pl->stream>>>(buf, list, pm, frac,
+                                                                    at<uint32_t>(pl, pl->L.maskw));
+  }
   static void assemble(cpra_plan_t pl, void* vol) {
     stepd_run<N, T>(at<C>(pl, pl->L.P), at<int>(pl, pl->L.csr_ptr), at<int>(pl, pl->L.csr_ent),
                     pl->p.insertion == CPRA_INSERT_BILINEAR ? at<T>(pl, pl->L.csr_w) : nullptr,
@@ -200,7 +214,7 @@ template <int N, typename T, typename AP> Ops ops_for() {
   return Ops{&Impl<N, T, AP>::twiddles, &Impl<N, T, AP>::prep,    &Impl<N, T, AP>::init,
              &Impl<N, T, AP>::step,     &Impl<N, T, AP>::assemble, &Impl<N, T, AP>::reload,
              &Impl<N, T, AP>::colerr,   &Impl<N, T, AP>::moments,  &Impl<N, T, AP>::twin,
-             &Impl<N, T, AP>::merge_avg};
+             &Impl<N, T, AP>::merge_avg, &Impl<N, T, AP>::shrinkwrap};
 }
 
 

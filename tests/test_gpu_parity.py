@@ -264,6 +264,36 @@ def test_step_d_bilinear(torch, N, Np, real):
         assert np.abs(got - ref).max() <= (1e-4 if real == F32 else 1e-10) * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("real", [F32, F64])
+@pytest.mark.parametrize("N,Np", [(64, 4), (512, 2)])
+def test_shrinkwrap(torch, N, Np, real):
+    """Shrinkwrap support update from the GPU's own estimates (fed to the oracle as well): the
+    supports agree bit for bit except where the blurred object is within rounding of the
+    threshold; the next iteration runs with the new support."""
+    import paper_2402_05283_amd as cp
+    from oracle import cpra as C
+    scan = make_scan(1, N=N, Np=Np)
+    banner(f"shrinkwrap N={N} real={real}")
+    plan = cp.Plan(N, Np, theta=scan["theta"], n_ei=5, real=real, seed=scan["phase_seed"])
+    plan.submit(0, torch.from_numpy(scan["I"]).cuda(), torch.from_numpy(scan["support"]).cuda())
+    assert np.array_equal(plan.support(), scan["support"])
+    plan.iterate(5, cp.HIO, 0.9)
+    torch.cuda.synchronize()
+    g = plan.objects().cpu().numpy().astype(np.float64)
+    sigma, thr = 1.5, 0.1
+    plan.shrinkwrap(sigma, thr)
+    got = plan.support().astype(bool)
+    for n in range(Np):
+        b = C.shrinkwrap_blur(g[n], sigma)
+        want = b >= thr * b.max()
+        near = np.abs(b - thr * b.max()) <= (1e-5 if real == F32 else 1e-12) * b.max()
+        assert np.array_equal(got[n][~near], want[~near])
+        assert want.sum() < scan["support"][n].sum()        # it did shrink
+    plan.iterate(5, cp.ER, 0.0)                             # the new support is in use
+    torch.cuda.synchronize()
+    assert np.all(plan.objects().cpu().numpy()[~got] == 0)
+
+
 def test_deterministic_and_homogeneous(torch):
     """Same inputs give bitwise-equal results; scaling I by 4 scales every iterate by exactly 2."""
     scan = make_scan(1, Np=6)
