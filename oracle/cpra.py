@@ -174,6 +174,32 @@ def couple(X: np.ndarray, present, alpha, wrap) -> np.ndarray:
     return out
 
 
+def couple_taps(X: np.ndarray, present, taps, wrap) -> np.ndarray:
+    """Eq. 4 with 2K+1 taps alpha_{-K..K} (taps[k + K] = alpha_k): new initial guesses
+    O_n <- sum_k alpha_k X_{n+k} over the periodic ring; a neighbour reached by wrapping round the
+    ring is t-mirrored under the mirror seam rule; absent neighbours drop out and the remaining
+    weights are rescaled to sum to 1.  Needs 2K+1 <= Np (each neighbour taken once)."""
+    Np = X.shape[0]
+    K = (len(taps) - 1) // 2
+    out = np.zeros_like(X)
+    for n in range(Np):
+        if not present[n]:
+            out[n] = X[n]
+            continue
+        terms = []
+        for k in range(-K, K + 1):
+            m = n + k
+            wrapped = m < 0 or m >= Np
+            m %= Np
+            if k != 0 and not present[m]:
+                continue
+            x = mirror_t(X[m]) if (wrapped and wrap == WRAP_MIRROR) else X[m]
+            terms.append((taps[k + K], x))
+        s = sum(w for w, _ in terms)
+        out[n] = sum((w / s) * x for w, x in terms)
+    return out
+
+
 def initial_object(A: np.ndarray, seed: int, n: int) -> np.ndarray:
     """W_0 object of angle n: Re F2^-1(A exp(i phi)), unmeasured pixels with amplitude 0."""
     N = A.shape[-1]
@@ -186,8 +212,9 @@ class Oracle:
     """Plain FP64 CPRA over one scan of Np angles (mirrors the C-ABI plan semantics)."""
 
     def __init__(self, N, Np, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=WRAP_MIRROR,
-                 positivity=True, seed=0):
+                 positivity=True, seed=0, taps=None):
         self.N, self.Np = int(N), int(Np)
+        self.taps = None if taps is None else tuple(float(a) for a in taps)   # 2K+1 taps, else alpha
         self.theta = (np.pi * np.arange(Np) / Np) if theta is None else np.asarray(theta, dtype=np.float64)
         self.alpha = tuple(float(a) for a in alpha)
         self.n_ei = int(n_ei)
@@ -223,7 +250,10 @@ class Oracle:
         for i in range(n_iter):
             if self.k % self.n_ei == 0:
                 self.present = self.landed.copy()
-                self.g = couple(self.g, self.present, self.alpha, self.wrap)
+                if self.taps is None:
+                    self.g = couple(self.g, self.present, self.alpha, self.wrap)
+                else:
+                    self.g = couple_taps(self.g, self.present, self.taps, self.wrap)
             estimate = (self.k + 1) % self.n_ei == 0
             for n in np.flatnonzero(self.present):
                 G = forward(self.g[n])

@@ -74,3 +74,33 @@ def test_slice_cells_closed_forms():
     assert np.array_equal(ky[0], (u + N // 2) % N)
     assert np.array_equal(kx[1], (-u + N // 2) % N)
     assert np.array_equal(ky[1], np.full(N, N // 2))
+
+
+def test_k_tap_coupling_reduces_and_closed_forms():
+    """2K+1 taps: the 3-tap case equals Eq. 4's three-tap form; a one-hot tap is a ring shift
+    (mirrored where it wraps); the plain-wrap ring sum is preserved; absent neighbours renormalise."""
+    from oracle import cpra as C
+    rng = np.random.default_rng(7)
+    Np, N = 7, 8
+    X = rng.standard_normal((Np, N, N))
+    allp = np.ones(Np, bool)
+    for wrap in (C.WRAP_MIRROR, C.WRAP_PLAIN):
+        assert np.allclose(C.couple_taps(X, allp, (0.1, 0.6, 0.3), wrap), C.couple(X, allp, (0.1, 0.6, 0.3), wrap),
+                           atol=1e-15)
+    # one-hot alpha_{+2}: O_n = X_{n+2}, mirrored for n = Np-2, Np-1 (the wrap)
+    taps = (0, 0, 1e-300, 0, 1.0)
+    Y = C.couple_taps(X, allp, taps, C.WRAP_MIRROR)
+    for n in range(Np):
+        want = X[(n + 2) % Np] if n + 2 < Np else C.mirror_t(X[(n + 2) % Np])
+        assert np.allclose(Y[n], want, atol=1e-12)
+    # plain wrap: every column of the circulant sums to 1, so the ring sum is kept
+    taps5 = (0.05, 0.15, 0.5, 0.2, 0.1)
+    Z = C.couple_taps(X, allp, taps5, C.WRAP_PLAIN)
+    assert np.allclose(Z.sum(0), X.sum(0), atol=1e-12)
+    # absent neighbour n+1 of n = 2: its weight drops, the rest rescale
+    pres = allp.copy()
+    pres[3] = False
+    W = C.couple_taps(X, pres, taps5, C.WRAP_PLAIN)
+    s = 0.05 + 0.15 + 0.5 + 0.1
+    assert np.allclose(W[2], (0.05 * X[0] + 0.15 * X[1] + 0.5 * X[2] + 0.1 * X[4]) / s, atol=1e-13)
+    assert np.array_equal(W[3], X[3])
