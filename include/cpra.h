@@ -73,6 +73,11 @@ typedef struct {
   int32_t insertion;     /* step D's interpolation: CPRA_INSERT_NEAREST (nearest voxel,
                             plain average) or CPRA_INSERT_BILINEAR (four cells around the
                             slice point, weighted average sum(w E) / sum(w))          */
+  const double* taps;    /* NULL, or n_taps = 2K+1 weights alpha_{-K..K} of Eq. 4 (copied
+                            at plan creation; >= 0, sum 1, centre > 0, 2K+1 <= Np), in
+                            place of alpha: O_n <- sum_k alpha_k X_{n+k}, periodic, the
+                            wrapped neighbours t-mirrored under CPRA_WRAP_MIRROR        */
+  int32_t n_taps;        /* 0 (use alpha) or odd >= 3                                   */
 } cpra_params;
 
 /*

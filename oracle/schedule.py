@@ -64,11 +64,12 @@ class GuessSet:
     """N_r reconstructions of one scan under the paper's schedule."""
 
     def __init__(self, N, Np, n_guess, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=C.WRAP_MIRROR,
-                 positivity=True, seed=0):
+                 positivity=True, seed=0, taps=None):
         self.N, self.Np, self.R = int(N), int(Np), int(n_guess)
         self.theta = (np.pi * np.arange(Np) / Np) if theta is None else np.asarray(theta, dtype=np.float64)
         self.alpha = tuple(float(a) for a in alpha)
         self.n_ei, self.wrap, self.positivity, self.seed = int(n_ei), int(wrap), bool(positivity), int(seed)
+        self.taps = None if taps is None else tuple(float(a) for a in taps)    # 2K+1 taps, else alpha
         self.A = np.zeros((Np, N, N))
         self.S = np.zeros((Np, N, N), dtype=bool)
         self.g = np.zeros((self.R, Np, N, N))
@@ -96,6 +97,9 @@ class GuessSet:
 
     def couple_one(self, r, n):
         """Eq. 4 for PO n of guess r from the current objects (all angles present)."""
+        if self.taps is not None:
+            self.g[r, n] = C.couple_taps(self.g[r], np.ones(self.Np, bool), self.taps, self.wrap)[n]
+            return
         (l, wl, ml), w0, (rr, wr, mr) = C.coupling_weights(self.Np, np.ones(self.Np, bool), self.alpha,
                                                            self.wrap)[n]
         X = self.g[r]
@@ -122,7 +126,10 @@ class GuessSet:
         """Step B, data-parallel form: every PO re-initialised from the previous episode."""
         for _ in range(n_episodes):
             for r in range(self.R):
-                self.g[r] = C.couple(self.g[r], np.ones(self.Np, bool), self.alpha, self.wrap)
+                if self.taps is None:
+                    self.g[r] = C.couple(self.g[r], np.ones(self.Np, bool), self.alpha, self.wrap)
+                else:
+                    self.g[r] = C.couple_taps(self.g[r], np.ones(self.Np, bool), self.taps, self.wrap)
                 for n in range(self.Np):
                     self.iterate_po(r, n, self.n_ei, algo, beta)
 

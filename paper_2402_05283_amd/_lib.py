@@ -49,6 +49,8 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("n_guess", ctypes.c_int32),
         ("insertion", ctypes.c_int32),
+        ("taps", ctypes.POINTER(ctypes.c_double)),
+        ("n_taps", ctypes.c_int32),
     ]
 
 
@@ -115,7 +117,7 @@ def iterate_batch(plans, n_iter, algo=HIO, beta=0.9):
 
 
 def make_params(N, Np, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=WRAP_MIRROR, positivity=True,
-                real=REAL_F32, amp=AMP_F32, seed=0, n_guess=1, insertion=0):
+                real=REAL_F32, amp=AMP_F32, seed=0, n_guess=1, insertion=0, taps=None):
     p = Params()
     p.struct_size = ctypes.sizeof(Params)
     p.N, p.Np = int(N), int(Np)
@@ -131,6 +133,12 @@ def make_params(N, Np, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=WRAP_MIR
     p.seed = int(seed) % (1 << 64)
     p.n_guess = int(n_guess)
     p.insertion = int(insertion)
+    p._taps_keep = None
+    if taps is not None:
+        tp = np.ascontiguousarray(taps, dtype=np.float64)
+        p._taps_keep = tp
+        p.taps = tp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.n_taps = len(tp)
     return p
 
 
@@ -164,11 +172,13 @@ class Plan:
     """One scan on the current device: owns a torch workspace tensor and a library plan."""
 
     def __init__(self, N, Np, theta=None, alpha=(0.2, 0.6, 0.2), n_ei=10, wrap=WRAP_MIRROR, positivity=True,
-                 real=REAL_F32, amp=AMP_F32, seed=0, stream=None, device=None, n_guess=1, insertion=0):
+                 real=REAL_F32, amp=AMP_F32, seed=0, stream=None, device=None, n_guess=1, insertion=0,
+                 taps=None):
         import torch
         self.torch = torch
         lib = load()
-        self.params = make_params(N, Np, theta, alpha, n_ei, wrap, positivity, real, amp, seed, n_guess, insertion)
+        self.params = make_params(N, Np, theta, alpha, n_ei, wrap, positivity, real, amp, seed, n_guess, insertion,
+                                  taps)
         self.N, self.Np = int(N), int(Np)
         self.R = max(1, int(n_guess))
         self.real = real

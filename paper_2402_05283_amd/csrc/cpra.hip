@@ -18,6 +18,7 @@
 using namespace cpra;
 
 static_assert(sizeof(cpra::Coupling) == sizeof(cpra_host::Coupling), "coupling record layout");
+static_assert(sizeof(cpra::Tap) == sizeof(cpra_host::Tap), "tap record layout");
 
 using namespace cpra_impl;
 
@@ -84,6 +85,17 @@ cpra_status validate(const cpra_params* p, std::string& msg) {
   if (p->struct_size != sizeof(cpra_params)) { msg = "params.struct_size mismatch"; return CPRA_ERR_ARG; }
   if (!size_supported(p->N)) { msg = "N must be 64, 128, 256, 512 or 1024"; return CPRA_ERR_UNSUPPORTED; }
   if (p->Np < 1) { msg = "Np must be >= 1"; return CPRA_ERR_ARG; }
+  if (p->n_taps != 0) {
+    if (p->n_taps < 3 || p->n_taps % 2 == 0 || !p->taps) { msg = "n_taps must be 0 or an odd number >= 3 with taps set"; return CPRA_ERR_ARG; }
+    if (p->n_taps > p->Np) { msg = "2K+1 taps need Np >= 2K+1"; return CPRA_ERR_ARG; }
+    double ts = 0.0;
+    for (int i = 0; i < p->n_taps; ++i) {
+      if (!(p->taps[i] >= 0.0) || !std::isfinite(p->taps[i])) { msg = "taps must be finite and >= 0"; return CPRA_ERR_ARG; }
+      ts += p->taps[i];
+    }
+    if (std::fabs(ts - 1.0) > 1e-12) { msg = "taps must sum to 1"; return CPRA_ERR_ARG; }
+    if (!(p->taps[p->n_taps / 2] > 0.0)) { msg = "the centre tap must be > 0"; return CPRA_ERR_ARG; }
+  }
   if (p->insertion != CPRA_INSERT_NEAREST && p->insertion != CPRA_INSERT_BILINEAR) {
     msg = "bad insertion"; return CPRA_ERR_ARG;
   }
@@ -146,6 +158,7 @@ Layout layout_of(const cpra_params* p) {
   L.prep_part = take(Np * cpra::kPrepBlocks * 12);
   L.mtab = take(S * 3 * 8 + S * 4 * 4 + (S / Np) * 64 + 256);   // step C tables
   L.swk = take((N + 1) * rs);                                      // shrinkwrap window taps
+  L.ctab = take(p->n_taps > 3 ? S * p->n_taps * sizeof(cpra::Tap) : 0);   // Eq. 4, 2K+1 taps
   L.total = o;
   return L;
 }
@@ -197,6 +210,11 @@ cpra_status upload_tables(cpra_plan_t pl) {
   // one ring per guess: the table of the Np angles, offset to each guess's slots
   std::vector<cpra_host::Coupling> one;
   cpra_host::coupling_table(Np, pl->present.data(), pl->p.alpha, pl->p.wrap == CPRA_WRAP_MIRROR, one);
+  // an absent neighbour has weight 0; point it at the angle itself so that no unset plane is read
+  for (int n = 0; n < Np; ++n) {
+    if (one[n].wl == 0.0) { one[n].left = n; one[n].mirror_left = 0; }
+    if (one[n].wr == 0.0) { one[n].right = n; one[n].mirror_right = 0; }
+  }
   pl->coup_h.resize((size_t)R * Np);
   pl->alist_h.clear();
   for (int r = 0; r < R; ++r)
@@ -209,6 +227,20 @@ cpra_status upload_tables(cpra_plan_t pl) {
     }
   HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.coup, pl->coup_h.data(), pl->coup_h.size() * sizeof(cpra::Coupling),
                             hipMemcpyHostToDevice, pl->stream));
+  if (pl->K > 1) {   // Eq. 4 with 2K+1 taps: one table per guess ring
+    std::vector<cpra_host::Tap> t1;
+    cpra_host::tap_table(Np, pl->present.data(), pl->taps.data(), pl->K, pl->p.wrap == CPRA_WRAP_MIRROR, t1);
+    const int nt = 2 * pl->K + 1;
+    pl->tap_h.resize((size_t)R * Np * nt);
+    for (int r = 0; r < R; ++r)
+      for (size_t i = 0; i < (size_t)Np * nt; ++i) {
+        cpra_host::Tap t = t1[i];
+        t.nb += r * Np;
+        pl->tap_h[(size_t)r * Np * nt + i] = t;
+      }
+    HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.ctab, pl->tap_h.data(), pl->tap_h.size() * sizeof(cpra::Tap),
+                              hipMemcpyHostToDevice, pl->stream));
+  }
   if (!pl->alist_h.empty())
     HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist, pl->alist_h.data(), pl->alist_h.size() * 4,
                               hipMemcpyHostToDevice, pl->stream));
@@ -247,6 +279,13 @@ cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t 
   pl->p = *params;
   pl->R = std::max(1, params->n_guess);
   pl->p.n_guess = pl->R;
+  if (params->n_taps == 3) {               // three taps: the fused coupling with alpha
+    for (int i = 0; i < 3; ++i) pl->p.alpha[i] = params->taps[i];
+  } else if (params->n_taps > 3) {
+    pl->taps.assign(params->taps, params->taps + params->n_taps);
+    pl->K = params->n_taps / 2;
+  }
+  pl->p.taps = nullptr;
   pl->theta.resize(params->Np);
   for (int n = 0; n < params->Np; ++n)
     pl->theta[n] = params->theta ? params->theta[n] : cpra_host::default_theta(n, params->Np);
@@ -356,6 +395,19 @@ cpra_status cpra_submit_angles(cpra_plan_t pl, int32_t first, int32_t count, con
   return CPRA_OK;
 }
 
+// one iteration of the listed slots; a boundary couples (Eq. 4) on the way in: fused into the
+// passes for three taps, or as a pass of its own into the Pmid scratch for 2K+1 > 3 taps
+static void do_step(cpra_plan_t pl, const Ops& ops, const int* al, int nact, bool boundary, bool inplace,
+                    int mode, double beta, double* ep) {
+  if (boundary && pl->K > 1) {
+    const int gout = inplace ? pl->cur : (pl->cur ^ 1);
+    ops.couple_taps(pl, al, nact, pl->cur, gout);
+    ops.step(pl, al, nact, false, false, mode, beta, ep, pl->ws + pl->L.Pmid, gout);
+  } else {
+    ops.step(pl, al, nact, boundary, inplace, mode, beta, ep, nullptr, -1);
+  }
+}
+
 // one iteration of one plan with no error history: episode bookkeeping, then the two passes
 static cpra_status step_once(cpra_plan_t pl, const Ops& ops, int32_t algo, double beta) {
   const bool boundary = (pl->k % pl->p.n_ei) == 0;
@@ -370,7 +422,7 @@ static cpra_status step_once(cpra_plan_t pl, const Ops& ops, int32_t algo, doubl
   const int nact = (int)pl->alist_h.size();
   const bool estimate = ((pl->k + 1) % pl->p.n_ei) == 0;
   const int mode = estimate ? 2 : mode_of(algo);
-  ops.step(pl, at<int>(pl, pl->L.alist), nact, boundary, false, mode, beta, nullptr);
+  do_step(pl, ops, at<int>(pl, pl->L.alist), nact, boundary, false, mode, beta, nullptr);
   LAUNCHCHK(pl);
   if (boundary) pl->cur ^= 1;
   pl->k += 1;
@@ -457,7 +509,7 @@ cpra_status cpra_iterate(cpra_plan_t pl, int32_t n_iter, int32_t algo, double be
     const bool estimate = ((pl->k + 1) % pl->p.n_ei) == 0;
     const int mode = estimate ? 2 : mode_of(algo);
     double* ep = err_out ? at<double>(pl, pl->L.errpart) + (size_t)slot * nact * pl->ntiles : nullptr;
-    ops.step(pl, at<int>(pl, pl->L.alist), nact, boundary, false, mode, beta, ep);
+    do_step(pl, ops, at<int>(pl, pl->L.alist), nact, boundary, false, mode, beta, ep);
     LAUNCHCHK(pl);
     if (boundary) pl->cur ^= 1;
     pl->k += 1;
@@ -497,7 +549,7 @@ cpra_status run_po(cpra_plan_t pl, const Ops& ops, const int* d_list, int n_it, 
   for (int it = 0; it < n_it; ++it) {
     const int mode = it == n_it - 1 ? 2 : mode_of(algo);
     double* ep = err ? errpart + (size_t)(it % kErrSlots) * R * pl->ntiles : nullptr;
-    ops.step(pl, d_list, R, couple && it == 0, true, mode, beta, ep);
+    do_step(pl, ops, d_list, R, couple && it == 0, true, mode, beta, ep);
     LAUNCHCHK(pl);
     if (err && (it % kErrSlots == kErrSlots - 1 || it == n_it - 1)) {
       const int ns = it % kErrSlots + 1;

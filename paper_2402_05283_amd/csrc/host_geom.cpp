@@ -114,4 +114,25 @@ void coupling_table(int Np, const uint8_t* present, const double alpha[3], int w
   }
 }
 
+// Eq. 4 with 2K+1 taps: per angle n the terms k = -K..K (slot n + k on the periodic ring,
+// t-mirrored where it wraps under the mirror rule); absent neighbours get weight 0 (and point at
+// n itself), the rest are rescaled to sum to 1.  Needs 2K+1 <= Np.
+void tap_table(int Np, const uint8_t* present, const double* taps, int K, int wrap_mirror, std::vector<Tap>& out) {
+  const int nt = 2 * K + 1;
+  out.assign((size_t)Np * nt, Tap{0, 0, 0.0});
+  for (int n = 0; n < Np; ++n) {
+    double s = 0.0;
+    for (int k = -K; k <= K; ++k) {
+      const int m = n + k;
+      const bool wrapped = m < 0 || m >= Np;
+      const int mm = ((m % Np) + Np) % Np;
+      const bool here = k == 0 || present == nullptr || present[mm];
+      Tap t{here ? mm : n, (here && wrapped && wrap_mirror) ? 1 : 0, here ? taps[k + K] : 0.0};
+      out[(size_t)n * nt + (k + K)] = t;
+      s += t.w;
+    }
+    for (int q = 0; q < nt; ++q) out[(size_t)n * nt + q].w /= s;
+  }
+}
+
 }  // namespace cpra_host

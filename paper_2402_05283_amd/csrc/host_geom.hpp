@@ -12,7 +12,13 @@ struct Coupling {
   double wl, w0, wr;
 };
 
+struct Tap {
+  int nb, mirror;
+  double w;
+};
+
 double default_theta(int n, int Np);
+void tap_table(int Np, const uint8_t* present, const double* taps, int K, int wrap_mirror, std::vector<Tap>& out);
 void slice_cells(int N, int Np, const double* theta, int32_t* kx, int32_t* ky);
 void insertion_csr(int N, int Np, const double* theta, std::vector<int32_t>& row_ptr,
                    std::vector<int32_t>& entries);

@@ -16,7 +16,7 @@ namespace cpra_impl {
 
 struct Layout {
   size_t P, Pmid, g0, g1, A2, ampscale, maskw, den, tw, coup, alist, errpart, errhist, flags, stage_I,
-      stage_S, csr_ptr, csr_ent, csr_w, cnt_inv, plane, prep_part, mtab, swk, total;
+      stage_S, csr_ptr, csr_ent, csr_w, cnt_inv, plane, prep_part, mtab, swk, ctab, total;
   int zc;   // z-planes per step-D chunk
 };
 
@@ -25,6 +25,8 @@ struct Layout {
 struct cpra_plan_s {
   cpra_params p{};
   int R = 1;                   // guesses (independent reconstructions); slot r * Np + n
+  std::vector<double> taps;    // 2K+1 taps of Eq. 4 when K >= 2 (else alpha[3] and the fused path)
+  int K = 1;
   std::vector<double> theta;
   cpra_impl::Layout L{};
   char* ws = nullptr;
@@ -38,6 +40,7 @@ struct cpra_plan_s {
   std::string err;
   int ntiles = 0;
   std::vector<cpra_host::Coupling> coup_h;
+  std::vector<cpra_host::Tap> tap_h;
   std::vector<double> errhist_h;
   // optional per-pass event timing (measurement): triples (before col, between, after row)
   bool timing = false;
@@ -66,7 +69,7 @@ struct Ops {
   void (*twiddles)(cpra_plan_t);
   void (*prep)(cpra_plan_t, const float*, const uint8_t*, int, int);
   void (*init)(cpra_plan_t, const int*, int, int);
-  void (*step)(cpra_plan_t, const int*, int, bool, bool, int, double, double*);
+  void (*step)(cpra_plan_t, const int*, int, bool, bool, int, double, double*, const void*, int);
   void (*assemble)(cpra_plan_t, void*);
   void (*reload)(cpra_plan_t, const int*, int, int);
   void (*colerr)(cpra_plan_t, const int*, int, double*);
@@ -74,6 +77,7 @@ struct Ops {
   void (*twin)(cpra_plan_t, const int*, const int*, int, double*);
   void (*merge_avg)(cpra_plan_t, int, const int*, const int*, const int*, void*);
   void (*shrinkwrap)(cpra_plan_t, const int*, int, int, double);
+  void (*couple_taps)(cpra_plan_t, const int*, int, int, int);
 };
 
 template <int N, typename T, typename AP>
@@ -113,8 +117,10 @@ struct Impl {
   }
   // one iteration of the listed slots; couple: Eq. 4 on the way in, from buffer cur into the other
   // buffer (Jacobi) or, with inplace, within buffer cur (the neighbours must not be listed)
+  // pin / gbuf (when non-NULL / >= 0): column-pass input spectra and the g buffer to run on,
+  // instead of P and buffer cur (a K-tap boundary couples into the Pmid scratch first)
   static void step(cpra_plan_t pl, const int* al, int nact, bool couple, bool inplace, int mode, double beta,
-                   double* errpart) {
+                   double* errpart, const void* pin, int gbuf) {
     using CG = ColGeom<N>;
     using RG = RowGeom<N>;
     dim3 gc(CG::TILES, nact), bc(CG::R1 * CG::C);
@@ -125,7 +131,8 @@ struct Impl {
       if (e0) (void)hipEventRecord(e0, pl->stream);
     }
     auto launch = [&](auto kern, double* ep) {
-      kern<<<gc, bc, 0, pl->stream>>>(at<C>(pl, pl->L.P), at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2),
+      kern<<<gc, bc, 0, pl->stream>>>(pin ? reinterpret_cast<const C*>(pin) : at<C>(pl, pl->L.P),
+                                      at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2),
                                       at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw), al, cp, pl->p.Np, ep,
                                       CG::TILES, 0);
     };
@@ -147,8 +154,9 @@ struct Impl {
       }
     }
     if (e1) (void)hipEventRecord(e1, pl->stream);
-    T* gin = at<T>(pl, pl->cur ? pl->L.g1 : pl->L.g0);
-    T* gout = (couple && !inplace) ? at<T>(pl, pl->cur ? pl->L.g0 : pl->L.g1) : gin;
+    const int gb = gbuf >= 0 ? gbuf : pl->cur;
+    T* gin = at<T>(pl, gb ? pl->L.g1 : pl->L.g0);
+    T* gout = (couple && !inplace) ? at<T>(pl, gb ? pl->L.g0 : pl->L.g1) : gin;
     dim3 gr(N / RG::RPB, nact), br(RG::T * RG::RPB);
     auto row = couple ? k_row<N, T, true> : k_row<N, T, false>;
     row<<<gr, br, 0, pl->stream>>>(at<C>(pl, pl->L.Pmid), at<C>(pl, pl->L.P), gin, gout, at<uint32_t>(pl, pl->L.maskw),
@@ -200,6 +208,12 @@ struct Impl {
     k_shrink_mask<N, T, CB><<<dim3(N, count), 256, 0, pl->stream>>>(buf, list, pm, frac,
                                                                     at<uint32_t>(pl, pl->L.maskw));
   }
+  // Eq. 4 with 2K+1 taps for the listed slots: P -> Pmid, g[gin_buf] -> g[gout_buf]
+  static void couple_taps(cpra_plan_t pl, const int* al, int nact, int gin_buf, int gout_buf) {
+    k_couple_taps<N, T><<<dim3(N, nact), 256, 0, pl->stream>>>(
+        at<C>(pl, pl->L.P), at<C>(pl, pl->L.Pmid), at<T>(pl, gin_buf ? pl->L.g1 : pl->L.g0),
+        at<T>(pl, gout_buf ? pl->L.g1 : pl->L.g0), al, at<cpra::Tap>(pl, pl->L.ctab), 2 * pl->K + 1);
+  }
   static void assemble(cpra_plan_t pl, void* vol) {
     stepd_run<N, T>(at<C>(pl, pl->L.P), at<int>(pl, pl->L.csr_ptr), at<int>(pl, pl->L.csr_ent),
                     pl->p.insertion == CPRA_INSERT_BILINEAR ? at<T>(pl, pl->L.csr_w) : nullptr,
@@ -214,7 +228,7 @@ template <int N, typename T, typename AP> Ops ops_for() {
   return Ops{&Impl<N, T, AP>::twiddles, &Impl<N, T, AP>::prep,    &Impl<N, T, AP>::init,
              &Impl<N, T, AP>::step,     &Impl<N, T, AP>::assemble, &Impl<N, T, AP>::reload,
              &Impl<N, T, AP>::colerr,   &Impl<N, T, AP>::moments,  &Impl<N, T, AP>::twin,
-             &Impl<N, T, AP>::merge_avg, &Impl<N, T, AP>::shrinkwrap};
+             &Impl<N, T, AP>::merge_avg, &Impl<N, T, AP>::shrinkwrap, &Impl<N, T, AP>::couple_taps};
 }
 
 

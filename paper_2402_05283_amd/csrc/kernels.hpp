@@ -122,6 +122,50 @@ struct Coupling {   // per angle, used at episode boundaries
   double wl, w0, wr;
 };
 
+struct Tap {        // one term of Eq. 4 with 2K+1 taps: weight w on slot nb, t-mirrored or not
+  int nb, mirror;
+  double w;
+};
+
+// Eq. 4 with 2K+1 taps as a pass of its own at an episode boundary: for every listed slot,
+// Pc = sum_k w_k M_k(P_nb_k) into Pout (packed half spectra, layout pix<N>; the mirror
+// conjugates every entry but the packed DC/Nyquist column) and gc = sum_k w_k M_k(g_nb_k) into
+// gout (M: t -> N - t).  grid (N rows, count); the neighbours of a listed slot are not listed
+// when gin == gout.
+template <int N, typename T>
+__global__ void __launch_bounds__(256) k_couple_taps(const cx<T>* __restrict__ P, cx<T>* __restrict__ Pout,
+                                                     const T* gin, T* gout, const int* __restrict__ alist,
+                                                     const Tap* __restrict__ taps, int ntap) {
+  using C = cx<T>;
+  constexpr int H = N / 2, CB = PixCfg<N>::CB;
+  const int z = blockIdx.x, ai = blockIdx.y;
+  const int n = alist[ai];
+  const Tap* tp = taps + (size_t)n * ntap;
+  // spectra: row z holds H packed values; element j sits at pix(z, j)
+  for (int j = threadIdx.x; j < H; j += blockDim.x) {
+    const size_t e = pix<N>(z, j);
+    C acc = mk<C>((T)0, (T)0);
+    for (int q = 0; q < ntap; ++q) {
+      const Tap t = tp[q];
+      const C v = P[(size_t)t.nb * N * H + e];
+      const T sy = (t.mirror && j != 0) ? (T)-t.w : (T)t.w;
+      acc = mk<C>(acc.x + (T)t.w * v.x, acc.y + sy * v.y);
+    }
+    Pout[(size_t)n * N * H + e] = acc;
+  }
+  // objects: row z of the centred [z][t] plane
+  for (int t = threadIdx.x; t < N; t += blockDim.x) {
+    T acc = (T)0;
+    for (int q = 0; q < ntap; ++q) {
+      const Tap tq = tp[q];
+      const T* x = gin + ((size_t)tq.nb * N + z) * N;
+      acc += (T)tq.w * x[tq.mirror ? ((N - t) & (N - 1)) : t];
+    }
+    gout[((size_t)n * N + z) * N + t] = acc;
+  }
+  (void)CB;
+}
+
 // ---------------------------------------------------------------- amplitudes
 template <typename AP> struct AmpIO;
 template <> struct AmpIO<float2> {

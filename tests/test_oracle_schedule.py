@@ -139,3 +139,19 @@ def test_merge_undoes_shift_and_inversion_and_drops_the_worst():
         c = SC.mass_centre(merged[n])
         assert abs(c[0]) <= 0.5 + 1e-9 and abs(c[1]) <= 0.5 + 1e-9
     assert np.allclose(merged, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+def test_sweep_with_taps_propagates_two_steps(monkeypatch):
+    """Five taps (0, a, 1-a-b, 0, b) with no-op iterations: PO 1 takes PO 0's new value and PO 2's
+    old one (b); checks that the K-tap sweep reads the most recent objects two slots away."""
+    Np, a, b = 6, 0.3, 0.2
+    gs = SC.GuessSet(8, Np, 1, taps=(0.0, a, 1 - a - b, 0.0, b), wrap=C.WRAP_PLAIN, n_ei=1)
+    monkeypatch.setattr(gs, "iterate_po", lambda r, n, k, al, be: np.zeros(k))
+    gs.g[0] = 0.0
+    gs.g[0, 2] = 1.0
+    gs.sweep(1)
+    # PO 0 takes b X_2 (old 1); PO 1 takes a X_0(new) = a b; PO 2 takes a X_1(new) + (1-a-b) = ...
+    x0 = b * 1.0
+    x1 = a * x0
+    x2 = a * x1 + (1 - a - b) * 1.0
+    assert np.allclose(gs.g[0, :3, 0, 0], [x0, x1, x2], atol=1e-15)
