@@ -704,12 +704,6 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
       v[b] = Pn[pix<N>(a + R1 * b, j)];
     });
     typename AmpIO<AP>::pair_t amp[R2];
-    if (j0 != 0) {
-      sfor<0, R2>([&](auto kv) CPRA_INLINE {
-        constexpr int k = decltype(kv)::value;
-        amp[k] = AmpIO<AP>::raw(An + pix<N>(c + R2 * (k + R2 * sh), j));
-      });
-    }
     if (CPL) {
       const Coupling cp = coup[n];
       const T wl = (T)cp.wl, w0 = (T)cp.w0, wr = (T)cp.wr;
@@ -739,6 +733,14 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
       lds[cc * LSTRIDE + a * CC + col] = v[cc];
     });
     __syncthreads();
+    // the amplitude pairs, fetched here so that their latency overlaps step 2 without holding
+    // registers through step 1
+    if (j0 != 0) {
+      sfor<0, R2>([&](auto kv) CPRA_INLINE {
+        constexpr int k = decltype(kv)::value;
+        amp[k] = AmpIO<AP>::raw(An + pix<N>(c + R2 * (k + R2 * sh), j));
+      });
+    }
     // forward step 2: half sh of the R1-point DFT over a for this c
     sfor<0, R2>([&](auto kv) CPRA_INLINE {
       constexpr int k = decltype(kv)::value;
@@ -926,18 +928,20 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
   const bool t0 = (tau == 0);
   const int plane_lane = (threadIdx.x & ~(TT - 1)) + ((TT - tau) & (TT - 1));   // partner, for __shfl
 
-  // the current iterate of this thread's pixels, fetched up front so that
-  // its HBM latency overlaps the Pmid stream (HIO only)
+  // the current iterate of this thread's pixels (HIO and RAAR need it), fetched after the first
+  // LDS exchange of the C2R so that its latency overlaps the second half of the transform
   C gk[SPT][F1];
-  if (mode == 1 || mode == 4) {
-    sfor<0, SPT>([&](auto jv) CPRA_INLINE {
-      constexpr int jj = decltype(jv)::value;
-      sfor<0, F1>([&](auto mv) CPRA_INLINE {
-        constexpr int m1 = decltype(mv)::value;
-        gk[jj][m1] = *reinterpret_cast<const C*>(gin + rowr + 2 * (tau + TT * jj + F2 * m1));
+  auto load_gk = [&]() CPRA_INLINE {
+    if (mode == 1 || mode == 4) {
+      sfor<0, SPT>([&](auto jv) CPRA_INLINE {
+        constexpr int jj = decltype(jv)::value;
+        sfor<0, F1>([&](auto mv) CPRA_INLINE {
+          constexpr int m1 = decltype(mv)::value;
+          gk[jj][m1] = *reinterpret_cast<const C*>(gin + rowr + 2 * (tau + TT * jj + F2 * m1));
+        });
       });
-    });
-  }
+    }
+  };
   C sp[SPT][F1];
   C x[F2];
   if (mode == 3) {
@@ -991,6 +995,7 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
       });
     }
     __syncthreads();
+    load_gk();
     // ---- C2R step 2: for owned m2, F1-point IDFT over k1 -> x[m2 + F2 m1]
     sfor<0, SPT>([&](auto jv) CPRA_INLINE {
       constexpr int jj = decltype(jv)::value;
