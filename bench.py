@@ -408,6 +408,36 @@ def paper_schedule(cp, torch, scan, I, S, args):
             "kept": [int(k) for k in kept], "inverted": [bool(i) for i in inv]}
 
 
+def variants(cp, torch, scan, I, S, args):
+    """The algorithm variants on the same scan and kernels, timed on their own: 200 RAAR
+    iterations (beta 0.9); 200 HIO iterations with five coupling taps (a coupling pass of its own
+    at each of the 20 boundaries); one shrinkwrap support update (sigma 2, threshold 0.1); step D
+    with bilinear insertion."""
+    out = {}
+
+    def run(name, plan_kw, body):
+        plan = cp.Plan(N, NP, n_ei=N_EI, seed=scan["phase_seed"], **plan_kw)
+        plan.submit(0, I, S)
+        plan.iterate(N_EI, cp.HIO, BETA)                 # reach an episode end first
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = body(plan)
+        torch.cuda.synchronize()
+        out[name] = dict(seconds=round(time.perf_counter() - t0, 5), **(res or {}))
+        del plan
+
+    run("raar_200", {}, lambda p: (p.iterate(ITERS, cp.RAAR, BETA), None)[1])
+    out["raar_200"]["pattern_iterations_per_s"] = round(ITERS * NP / out["raar_200"]["seconds"], 1)
+    run("hio_200_five_taps", {"taps": (0.05, 0.15, 0.6, 0.15, 0.05)}, lambda p: (p.iterate(ITERS, cp.HIO, BETA), None)[1])
+    out["hio_200_five_taps"]["pattern_iterations_per_s"] = round(ITERS * NP / out["hio_200_five_taps"]["seconds"], 1)
+    run("shrinkwrap", {}, lambda p: (p.shrinkwrap(2.0, 0.1), None)[1])
+    vol = torch.empty((N, N, N), dtype=torch.float32, device=I.device)
+    run("step_d_bilinear", {"insertion": cp.INSERT_BILINEAR}, lambda p: (p.assemble_volume(vol), None)[1])
+    run("step_d_nearest", {}, lambda p: (p.assemble_volume(vol), None)[1])
+    del vol
+    return out
+
+
 def quality_error_only(torch, obj, A_nat, den):
     err = []
     for c0 in range(0, obj.shape[0], 60):
@@ -551,6 +581,9 @@ def main():
     if not args.no_compare and args.iters == ITERS and not args.amp16:
         print("[bench] plain per-angle comparison", file=sys.stderr, flush=True)
         out["vs_plain_per_angle"] = plain_comparison(cp, torch, scan, I, S, args, iter_ms)
+    if not args.no_compare and args.iters == ITERS and not args.amp16:
+        print("[bench] algorithm variants", file=sys.stderr, flush=True)
+        out["variants"] = variants(cp, torch, scan, I, S, args)
     if args.guesses > 0 and args.iters == ITERS and not args.amp16:
         print(f"[bench] paper schedule, {args.guesses} guesses", file=sys.stderr, flush=True)
         out["paper_schedule"] = paper_schedule(cp, torch, scan, I, S, args)
