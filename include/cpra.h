@@ -247,6 +247,35 @@ cpra_status cpra_load_objects(cpra_plan_t plan, const void* objects, int32_t ptr
  */
 cpra_status cpra_assemble_volume(cpra_plan_t plan, void* d_volume);
 
+/*
+ * Bytes of device workspace cpra_refine_volume needs for these parameters
+ * (about N^3 x (4 x the real size + 1)).  Host-only.
+ */
+cpra_status cpra_refine_workspace_size(const cpra_params* params, size_t* bytes);
+
+/*
+ * 3D refinement after step D (the tomographic iterations that follow the
+ * Fourier-slice insertion): starts from the step-D volume of the current
+ * estimates and runs n_iter error-reduction iterations in 3D.
+ *  - Fourier constraint: the Hermitian part (E(k) + conj E(-k))/2 of the
+ *    inserted spectrum on every measured (k_y, k_x) cell and its mirror, for
+ *    all k_z; other cells free.  As the insertion fills whole k_z lines, this
+ *    is applied per z-plane in the (z, k_y, k_x) domain (2D transforms only).
+ *  - Real-space constraint: the intersection over the present angles of the
+ *    back-projected 2D supports (voxel (z, y, x), centred, is kept when
+ *    t = floor(y cos t_n - x sin t_n + 1/2), FP64, lies in angle n's support
+ *    at row z), and positivity if the plan has it.
+ *  - Every shrink_every iterations (0: never) the 3D support is replaced by
+ *    the 3D shrinkwrap of the volume: separable periodic Gaussian, window
+ *    +-ceil(4 sigma) normalised, kept where >= threshold * its maximum.
+ * Writes the refined N^3 volume ([z][y][x] centred, the plan's real type)
+ * to d_volume.  work: device, 256-byte aligned, cpra_refine_workspace_size
+ * bytes, the caller's.  ERR_STATE unless k mod n_ei == 0 and k > 0.
+ * Synchronises the stream.
+ */
+cpra_status cpra_refine_volume(cpra_plan_t plan, int32_t n_iter, int32_t shrink_every, double sigma,
+                               double threshold, void* work, size_t work_bytes, void* d_volume);
+
 /* Free the plan's host memory.  The workspace stays the caller's. */
 cpra_status cpra_destroy(cpra_plan_t plan);
 

@@ -30,7 +30,7 @@ EXPORTED = [
     "cpra_assemble_volume", "cpra_destroy", "cpra_last_error", "cpra_iteration_count", "cpra_slice_cells",
     "cpra_coupling_table", "cpra_set_kernel_timing", "cpra_kernel_timing", "cpra_load_objects",
     "cpra_iterate_batch", "cpra_prereconstruct", "cpra_sweep", "cpra_merge", "cpra_shrinkwrap",
-    "cpra_read_support",
+    "cpra_read_support", "cpra_refine_workspace_size", "cpra_refine_volume",
 ]
 
 
@@ -86,6 +86,9 @@ def load():
     lib.cpra_merge.argtypes = [c.c_void_p, c.c_int32, c.c_void_p, c.c_void_p]
     lib.cpra_shrinkwrap.argtypes = [c.c_void_p, c.c_double, c.c_double]
     lib.cpra_read_support.argtypes = [c.c_void_p, c.c_void_p]
+    lib.cpra_refine_workspace_size.argtypes = [P(Params), P(c.c_size_t)]
+    lib.cpra_refine_volume.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_double, c.c_double, c.c_void_p,
+                                       c.c_size_t, c.c_void_p]
     lib.cpra_last_error.argtypes = [c.c_void_p]
     lib.cpra_last_error.restype = c.c_char_p
     lib.cpra_iteration_count.argtypes = [c.c_void_p, P(c.c_int64)]
@@ -271,6 +274,21 @@ class Plan:
     def shrinkwrap(self, sigma, threshold):
         """Replace every present angle's support by the shrinkwrap of its current object."""
         _check(load().cpra_shrinkwrap(self.handle, float(sigma), float(threshold)), self.handle)
+
+    def refine_volume(self, n_iter, shrink_every=0, sigma=1.0, threshold=0.1, out=None):
+        """3D refinement after step D; returns the refined (N, N, N) volume."""
+        torch = self.torch
+        n = ctypes.c_size_t(0)
+        _check(load().cpra_refine_workspace_size(ctypes.byref(self.params), ctypes.byref(n)))
+        work = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        wp = (work.data_ptr() + 255) // 256 * 256
+        if out is None:
+            out = torch.empty((self.N, self.N, self.N), dtype=self.dtype, device=self.device)
+        self._enter()
+        _check(load().cpra_refine_volume(self.handle, int(n_iter), int(shrink_every), float(sigma), float(threshold),
+                                         ctypes.c_void_p(wp), n.value, ctypes.c_void_p(out.data_ptr())), self.handle)
+        self._leave(out, work)
+        return out
 
     def support(self):
         """The supports in use, (Np, N, N) uint8 (host)."""

@@ -760,6 +760,111 @@ cpra_status cpra_shrinkwrap(cpra_plan_t pl, double sigma, double threshold) {
   return CPRA_OK;
 }
 
+namespace {
+
+struct RefineLayout {
+  size_t qh, cb, s3, pmax, win, sc, list, total;
+};
+
+RefineLayout refine_layout(const cpra_params* p) {
+  const size_t N = p->N, Np = p->Np, N3 = N * N * N;
+  const size_t rs = p->real_type == CPRA_REAL_F64 ? 8 : 4;
+  RefineLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+  L.qh = take(N3 * 2 * rs);
+  L.cb = take(N3 * 2 * rs);
+  L.s3 = take(N3);
+  L.pmax = take((N * N / 8 + 1) * 8);
+  L.win = take((N + 1) * rs);
+  L.sc = take(Np * 16);
+  L.list = take((Np + N) * 4);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+cpra_status cpra_refine_workspace_size(const cpra_params* params, size_t* bytes) {
+  std::string msg;
+  cpra_status st = validate(params, msg);
+  if (st != CPRA_OK) return fail(nullptr, st, "%s", msg.c_str());
+  if (!bytes) return fail(nullptr, CPRA_ERR_ARG, "bytes is NULL");
+  *bytes = refine_layout(params).total;
+  return CPRA_OK;
+}
+
+cpra_status cpra_refine_volume(cpra_plan_t pl, int32_t n_iter, int32_t shrink_every, double sigma, double threshold,
+                               void* work, size_t work_bytes, void* d_volume) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
+  if (!d_volume) return fail(pl, CPRA_ERR_ARG, "d_volume is NULL");
+  if (n_iter < 0 || shrink_every < 0) return fail(pl, CPRA_ERR_ARG, "n_iter and shrink_every must be >= 0");
+  const int N = pl->p.N, Np = pl->p.Np;
+  if (shrink_every > 0) {
+    if (!(sigma > 0.0) || !(4.0 * sigma <= N / 2 - 1))
+      return fail(pl, CPRA_ERR_ARG, "sigma must be > 0 with ceil(4 sigma) < N/2");
+    if (!(threshold > 0.0 && threshold <= 1.0)) return fail(pl, CPRA_ERR_ARG, "threshold must be in (0, 1]");
+  }
+  const RefineLayout RL = refine_layout(&pl->p);
+  if (!work || (reinterpret_cast<uintptr_t>(work) % kAlign) != 0)
+    return fail(pl, CPRA_ERR_ARG, "work must be non-NULL and 256-byte aligned");
+  if (work_bytes < RL.total)
+    return fail(pl, CPRA_ERR_OOM, "refinement workspace has %zu bytes, needs %zu", work_bytes, RL.total);
+  if (pl->k == 0 || pl->k % pl->p.n_ei != 0)
+    return fail(pl, CPRA_ERR_STATE, "the refinement starts from step D at an episode end (k=%lld)", (long long)pl->k);
+  char* w = reinterpret_cast<char*>(work);
+  // present data angles and their (sin, cos); then 0 .. N-1 (the planes as slots for the blur)
+  std::vector<int32_t> list;
+  std::vector<double> sc;
+  for (int n = 0; n < Np; ++n)
+    if (pl->present[n]) {
+      list.push_back(n);
+      sc.push_back(std::sin(pl->theta[n]));
+      sc.push_back(std::cos(pl->theta[n]));
+    }
+  if (list.empty()) return fail(pl, CPRA_ERR_STATE, "no angle is present");
+  const int count = (int)list.size();
+  for (int z = 0; z < N; ++z) list.push_back(z);
+  int W = 0;
+  std::vector<double> k;
+  if (shrink_every > 0) {
+    W = (int)std::ceil(4.0 * sigma);
+    k.resize(2 * W + 1);
+    double ks = 0.0;
+    for (int d = -W; d <= W; ++d) ks += (k[d + W] = std::exp(-(double)d * d / (2.0 * sigma * sigma)));
+    for (double& v : k) v /= ks;
+  }
+  std::vector<float> kf(k.begin(), k.end());
+  const bool f64 = pl->p.real_type == CPRA_REAL_F64;
+  HIPCHK(pl, hipMemcpyAsync(w + RL.list, list.data(), list.size() * 4, hipMemcpyHostToDevice, pl->stream));
+  HIPCHK(pl, hipMemcpyAsync(w + RL.sc, sc.data(), sc.size() * 8, hipMemcpyHostToDevice, pl->stream));
+  if (!k.empty())
+    HIPCHK(pl, hipMemcpyAsync(w + RL.win, f64 ? (const void*)k.data() : (const void*)kf.data(),
+                              k.size() * (f64 ? 8 : 4), hipMemcpyHostToDevice, pl->stream));
+  Ops ops = ops_of(pl->p);
+  ops.assemble(pl, d_volume);   // step D: the starting volume
+  LAUNCHCHK(pl);
+  RefineArgs a{};
+  a.vol = d_volume;
+  a.qh = w + RL.qh;
+  a.cb = w + RL.cb;
+  a.s3 = reinterpret_cast<uint8_t*>(w + RL.s3);
+  a.pmax = reinterpret_cast<double*>(w + RL.pmax);
+  a.win = w + RL.win;
+  a.sc = reinterpret_cast<const double*>(w + RL.sc);
+  a.list = reinterpret_cast<const int*>(w + RL.list);
+  a.count = count;
+  a.n_iter = n_iter;
+  a.shrink_every = shrink_every;
+  a.W = W;
+  a.threshold = threshold;
+  ops.refine(pl, a);
+  LAUNCHCHK(pl);
+  HIPCHK(pl, hipStreamSynchronize(pl->stream));   // host tables go out of scope
+  return CPRA_OK;
+}
+
 cpra_status cpra_read_support(cpra_plan_t pl, uint8_t* out) {
   if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
   if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");

@@ -10,6 +10,7 @@
 #include "kernels.hpp"
 #include "merge.hpp"
 #include "shrink.hpp"
+#include "refine.hpp"
 #include "stepd.hpp"
 
 namespace cpra_impl {
@@ -65,6 +66,20 @@ using namespace cpra;
 
 template <typename X> X* at(cpra_plan_t pl, size_t off) { return reinterpret_cast<X*>(pl->ws + off); }
 
+// device buffers and settings of one 3D refinement (the caller's refinement workspace)
+struct RefineArgs {
+  void* vol;          // N^3 real: the step-D volume in, the refined volume out
+  void* qh;           // N^3 complex: measured mixed-domain values (NaN = free)
+  void* cb;           // N^3 complex: row spectra of the iterate; blur scratch
+  uint8_t* s3;        // N^3 support
+  double* pmax;       // blur maxima (N * N / 8 + 1)
+  void* win;          // blur window taps (2W + 1)
+  const double* sc;   // (sin, cos) per listed angle
+  const int* list;    // present data angles
+  int count, n_iter, shrink_every, W;
+  double threshold;
+};
+
 struct Ops {
   void (*twiddles)(cpra_plan_t);
   void (*prep)(cpra_plan_t, const float*, const uint8_t*, int, int);
@@ -78,6 +93,7 @@ struct Ops {
   void (*merge_avg)(cpra_plan_t, int, const int*, const int*, const int*, void*);
   void (*shrinkwrap)(cpra_plan_t, const int*, int, int, double);
   void (*couple_taps)(cpra_plan_t, const int*, int, int, int);
+  void (*refine)(cpra_plan_t, const RefineArgs&);
 };
 
 template <int N, typename T, typename AP>
@@ -214,6 +230,39 @@ struct Impl {
         at<C>(pl, pl->L.P), at<C>(pl, pl->L.Pmid), at<T>(pl, gin_buf ? pl->L.g1 : pl->L.g0),
         at<T>(pl, gout_buf ? pl->L.g1 : pl->L.g0), al, at<cpra::Tap>(pl, pl->L.ctab), 2 * pl->K + 1);
   }
+  static void refine(cpra_plan_t pl, const RefineArgs& a) {
+    constexpr int CB = 8;
+    C* tw = at<C>(pl, pl->L.tw);
+    T* V = reinterpret_cast<T*>(a.vol);
+    C* Q = reinterpret_cast<C*>(a.qh);
+    C* Cb = reinterpret_cast<C*>(a.cb);
+    const bool bil = pl->p.insertion == CPRA_INSERT_BILINEAR;
+    k_ref_gather<N, T><<<dim3(N, N), 256, 0, pl->stream>>>(at<C>(pl, pl->L.P), at<int>(pl, pl->L.csr_ptr),
+                                                           at<int>(pl, pl->L.csr_ent),
+                                                           bil ? at<T>(pl, pl->L.csr_w) : nullptr,
+                                                           at<T>(pl, pl->L.cnt_inv), Q);
+    k_ref_support<N><<<dim3(N, N), 256, 0, pl->stream>>>(at<uint32_t>(pl, pl->L.maskw), a.list, a.sc, a.count,
+                                                         a.s3);
+    const unsigned rows = (unsigned)((size_t)N * N / kRefLines);
+    const int rthreads = StepdCfg<N>::R1 * kRefLines;
+    k_ref_rows<N, T, true><<<rows, rthreads, 0, pl->stream>>>(Cb, V, a.s3, pl->p.positivity, tw);
+    for (int it = 1; it <= a.n_iter; ++it) {
+      k_ref_cols<N, T><<<dim3(N / kRefLines, N), rthreads, 0, pl->stream>>>(Cb, Q, tw);
+      k_ref_rows<N, T, false><<<rows, rthreads, 0, pl->stream>>>(Cb, V, a.s3, pl->p.positivity, tw);
+      if (a.shrink_every > 0 && it % a.shrink_every == 0) {
+        // separable blur of V along x, y (planes as slots 0..N-1) and z into Cb, then threshold
+        T* buf = reinterpret_cast<T*>(Cb);
+        const T* win = reinterpret_cast<const T*>(a.win);
+        k_blur_rows<N, T><<<dim3(N, N), 256, 0, pl->stream>>>(V, a.list + a.count, win, a.W, buf);
+        k_blur_cols<N, T, CB><<<dim3(N / CB, N), 256, 0, pl->stream>>>(buf, win, a.W, a.pmax);
+        k_blur_z<N, T, CB><<<dim3(N / CB, N), 256, 0, pl->stream>>>(buf, win, a.W, a.pmax);
+        k_max_reduce<<<1, 256, 0, pl->stream>>>(a.pmax, N * (N / CB));
+        k_threshold<T><<<4096, 256, 0, pl->stream>>>(buf, (size_t)N * N * N, a.pmax + N * (N / CB), a.threshold,
+                                                     a.s3);
+        k_ref_rows<N, T, true><<<rows, rthreads, 0, pl->stream>>>(Cb, V, a.s3, pl->p.positivity, tw);
+      }
+    }
+  }
   static void assemble(cpra_plan_t pl, void* vol) {
     stepd_run<N, T>(at<C>(pl, pl->L.P), at<int>(pl, pl->L.csr_ptr), at<int>(pl, pl->L.csr_ent),
                     pl->p.insertion == CPRA_INSERT_BILINEAR ? at<T>(pl, pl->L.csr_w) : nullptr,
@@ -228,7 +277,8 @@ template <int N, typename T, typename AP> Ops ops_for() {
   return Ops{&Impl<N, T, AP>::twiddles, &Impl<N, T, AP>::prep,    &Impl<N, T, AP>::init,
              &Impl<N, T, AP>::step,     &Impl<N, T, AP>::assemble, &Impl<N, T, AP>::reload,
              &Impl<N, T, AP>::colerr,   &Impl<N, T, AP>::moments,  &Impl<N, T, AP>::twin,
-             &Impl<N, T, AP>::merge_avg, &Impl<N, T, AP>::shrinkwrap, &Impl<N, T, AP>::couple_taps};
+             &Impl<N, T, AP>::merge_avg, &Impl<N, T, AP>::shrinkwrap, &Impl<N, T, AP>::couple_taps,
+             &Impl<N, T, AP>::refine};
 }
 
 
