@@ -13,7 +13,8 @@ exactly j * r_frame iterations; each landed frame adds r_frame iterations of cre
 one adds r_final more.  r_frame and r_final are multiples of n_ei, so every chunk of work is whole
 episodes.  All scans with credit advance together, one episode per round, through
 cpra_iterate_batch (each plan on its own stream, so their kernels overlap on the device); at most
-`depth` episodes per scan are in flight, which bounds how long a frame submission can wait.
+`depth` episodes per scan are in flight, which bounds how long a frame submission can wait; a
+scan whose last frame has landed may queue up to `depth_final` and is issued first.
 """
 from __future__ import annotations
 
@@ -59,13 +60,13 @@ class Server:
     """
 
     def __init__(self, hbm_budget, n_ei=10, r_frame=None, r_final=50, algo=_lib.HIO, beta=0.9, depth=2,
-                 clock=time.perf_counter, plan_factory=None, batch_fn=None, stream_ctx=None):
+                 depth_final=8, clock=time.perf_counter, plan_factory=None, batch_fn=None, stream_ctx=None):
         r_frame = n_ei if r_frame is None else r_frame
         if r_frame % n_ei or r_final % n_ei or r_frame <= 0 or r_final < 0:
             raise ValueError("r_frame and r_final must be non-negative multiples of n_ei (r_frame > 0)")
         self.budget, self.used = int(hbm_budget), 0
         self.n_ei, self.r_frame, self.r_final = n_ei, r_frame, r_final
-        self.algo, self.beta, self.depth = algo, beta, depth
+        self.algo, self.beta, self.depth, self.depth_final = algo, beta, depth, max(depth, depth_final)
         self.clock = clock
         self.plan_factory = plan_factory or self._make_plan
         self.batch_fn = batch_fn or (lambda plans, n: _lib.iterate_batch(plans, n, self.algo, self.beta))
@@ -139,7 +140,12 @@ class Server:
                 s.n_submitted += 1
                 s.credit += self.r_frame + (self.r_final if s.n_submitted == s.n_expected else 0)
                 progressed = True
-        batch = [s for s in self.active if s.credit > 0 and len(s.in_flight) < self.depth]
+        # a scan whose last frame is in may queue more episodes (its latency is being measured),
+        # and goes first in the batch
+        def room(s):
+            return (self.depth_final if s.n_submitted == s.n_expected else self.depth) - len(s.in_flight)
+        batch = [s for s in self.active if s.credit > 0 and room(s) > 0]
+        batch.sort(key=lambda s: s.n_submitted != s.n_expected)
         if batch:
             self.batch_fn([s.plan for s in batch], self.n_ei)
             for s in batch:
