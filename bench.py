@@ -227,7 +227,13 @@ def serving_latency(cp, torch, scan, I, S, args):
     print(f"[bench] serving {len(jobs)} scans at {args.serve_fps} frames/s each "
           f"(~{T * args.serve_rounds + 0.25 * args.serve_scans:.0f} s)", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    done = serve.replay(srv, jobs)
+    count = [0]
+
+    def on_done(sc):
+        count[0] += 1
+        print(f"[bench] serving: {count[0]}/{len(jobs)} scans done, last-frame-to-volume "
+              f"{sc.latency_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    done = serve.replay(srv, jobs, on_done=on_done)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lat = np.array([d.latency_s for d in done]) * 1e3

@@ -199,9 +199,10 @@ class Job:
         self.next_frame = 0
 
 
-def replay(server, jobs, t0=None, idle_sleep=2e-4):
+def replay(server, jobs, t0=None, idle_sleep=2e-4, on_done=None):
     """Drive `server` with `jobs` in real time (frame arrival times relative to t0); returns the
-    finished Scan objects in job order once every scan has its volume."""
+    finished Scan objects in job order once every scan has its volume.  on_done(scan), if given,
+    is called as each scan finishes."""
     t0 = server.clock() if t0 is None else t0
     pending = sorted(jobs, key=lambda j: j.t_start)
     while True:
@@ -222,7 +223,11 @@ def replay(server, jobs, t0=None, idle_sleep=2e-4):
                 I, S = j.frames(j.next_frame)
                 server.push_frame(j.scan, j.next_frame, I, S, t=t0 + t_arr)
                 j.next_frame += 1
+        n_before = len(server.finished)
         progressed = server.step()
+        if on_done is not None:
+            for sc in server.finished[n_before:]:
+                on_done(sc)
         if all(j.scan is not None and j.scan.done for j in pending):
             return [j.scan for j in jobs]
         if not progressed:
