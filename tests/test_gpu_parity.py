@@ -419,6 +419,29 @@ def test_k_tap_coupling(torch, real):
     assert rel_l2(plan.objects().cpu().numpy(), gs.g) <= tol
 
 
+def test_precision_study_n512(torch):
+    """FP16 amplitude storage (per-angle power-of-two scale) against all-FP32, both against the FP64
+    oracle, on eight consecutive angles of the 512^3 cell scan: one HIO iteration from W_0 (with
+    the coupling), and ten ER iterations (one episode).  Prints the errors; bounds: FP32 1e-4,
+    FP16 2e-2."""
+    import paper_2402_05283_amd as cp
+    from oracle import cpra as C
+    scan = make_scan(4, angle_subset=list(range(100, 108)))
+    Np = 8
+    banner("precision study N=512")
+    res = {}
+    for name, sched, osched in (("hio1", [(1, HIO, 0.9)], [(1, C.HIO, 0.9)]),
+                                ("er10", [(10, ER, 0.0)], [(10, C.ER, 0.0)])):
+        o, _ = run_oracle(scan, osched)
+        for amp in (cp.AMP_F32, cp.AMP_F16):
+            _, obj, _ = run_gpu(scan, sched, real=F32, amp=amp)
+            res[(name, amp)] = rel_l2(obj, o.g)
+    print("precision study N=512, 8 angles, relative L2 vs FP64 oracle:",
+          {f"{k[0]}/{'fp16' if k[1] else 'fp32'}": f"{v:.2e}" for k, v in res.items()})
+    assert res[("hio1", cp.AMP_F32)] <= 1e-4 and res[("er10", cp.AMP_F32)] <= 1e-4
+    assert res[("hio1", cp.AMP_F16)] <= 2e-2 and res[("er10", cp.AMP_F16)] <= 2e-2
+
+
 def test_iterate_batch_matches_alone(torch):
     """cpra_iterate_batch: three scans of different N and Np, each on its own stream and at a
     different episode phase, advance together and end bit-identical to the same scans iterated
