@@ -35,12 +35,12 @@ __device__ __forceinline__ cx<T> spectrum_at(const cx<T>* Pn, int z, int u) {
 }
 
 // Rows: gather Q_z[ky][:] and inverse transform along kx.
-// Block: RB rows x R1 threads; grid: (N / RB, zc).
+// Block: RB rows x R1 threads; grid: (N / RB) * nz (see the mapping below).
 template <int N, typename T, int RB>
 __global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
     k_stepd_rows(const cx<T>* __restrict__ P, const int* __restrict__ ptr, const int* __restrict__ ent,
                  const T* __restrict__ wts, const T* __restrict__ cnt_inv, const cx<T>* __restrict__ tw,
-                 cx<T>* __restrict__ plane, int z0) {
+                 cx<T>* __restrict__ plane, int z0, int nz) {
   using C = cx<T>;
   constexpr int R1 = StepdCfg<N>::R1, R2 = StepdCfg<N>::R2, Q = R2 / R1, H = N / 2;
   static_assert(R1 * R2 == N && Q >= 1 && R2 % R1 == 0, "step D decomposition");
@@ -48,28 +48,58 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
   __shared__ C lds[RB * R2 * LS];
   const int a = threadIdx.x % R1;
   const int r = threadIdx.x / R1;
-  const int ky = blockIdx.x * RB + r;
-  const int zi = blockIdx.y;
+  // 1D grid of (N / RB) * nz workgroups.  The dispatcher deals consecutive workgroups round-robin
+  // to the 8 XCDs; the planes are split so that XCD x takes planes [x nz/8, (x+1) nz/8) whole,
+  // which keeps the rows z of all angles that those planes gather within one L2
+  constexpr int KB = N / RB;
+  const int L = blockIdx.x;
+  int zi, kyb;
+  if (nz % 8 == 0) {
+    const int x = L % 8, k = L / 8;
+    zi = x * (nz / 8) + k / KB;
+    kyb = k % KB;
+  } else {
+    zi = L / KB;
+    kyb = L % KB;
+  }
+  const int ky = kyb * RB + r;
   const int z = z0 + zi;
   C* L0 = lds + r * R2 * LS;
   C v[R2];
+  auto sample = [&](int e, int code) CPRA_INLINE -> C {
+    const int n = code / N, u = code % N;
+    C s = spectrum_at<N, T>(P + (size_t)n * N * H, z, u);
+    if (u & 1) { s.x = -s.x; s.y = -s.y; }
+    if (wts) s = cscale(s, wts[e]);      // bilinear insertion weight
+    return s;
+  };
+  // the cells go in groups of G, each gathered in three batches (entry ranges, first entries,
+  // the rest) so that the dependent loads of different cells overlap; per cell the entries are
+  // still summed in CSR order
+  constexpr int G = R2 < 8 ? R2 : 8;
+#pragma unroll
+  for (int g0 = 0; g0 < R2; g0 += G) {
+    int e0[G], e1[G], code[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const int cell = ky * N + a + R1 * (g0 + i);
+      e0[i] = ptr[cell];
+      e1[i] = ptr[cell + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < G; ++i) code[i] = e0[i] < e1[i] ? ent[e0[i]] : -1;
+#pragma unroll
+    for (int i = 0; i < G; ++i) v[g0 + i] = code[i] >= 0 ? sample(e0[i], code[i]) : mk<C>((T)0, (T)0);
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+      for (int e = e0[i] + 1; e < e1[i]; ++e) v[g0 + i] = cadd(v[g0 + i], sample(e, ent[e]));
+  }
 #pragma unroll
   for (int b = 0; b < R2; ++b) {
     const int kx = a + R1 * b;
-    const int cell = ky * N + kx;
-    C acc = mk<C>((T)0, (T)0);
-    const int e1 = ptr[cell + 1];
-    for (int e = ptr[cell]; e < e1; ++e) {
-      const int code = ent[e];
-      const int n = code / N, u = code % N;
-      C s = spectrum_at<N, T>(P + (size_t)n * N * H, z, u);
-      if (u & 1) { s.x = -s.x; s.y = -s.y; }
-      if (wts) s = cscale(s, wts[e]);      // bilinear insertion weight
-      acc = cadd(acc, s);
-    }
-    T f = cnt_inv[cell];
+    T f = cnt_inv[ky * N + kx];
     if ((ky + kx) & 1) f = -f;
-    v[b] = cscale(acc, f);
+    v[b] = cscale(v[b], f);
   }
   // inverse four-step along kx = a + R1 b -> x = c + R2 d
   dft<R2, +1>(v);
@@ -134,7 +164,7 @@ void stepd_run(const cx<T>* P, const int* ptr, const int* ent, const T* wts, con
   constexpr int CC = (256 / R1) < N ? (256 / R1) : N;
   for (int z0 = 0; z0 < N; z0 += zc) {
     const int nz = (N - z0) < zc ? (N - z0) : zc;
-    k_stepd_rows<N, T, RB><<<dim3(N / RB, nz), R1 * RB, 0, st>>>(P, ptr, ent, wts, cnt_inv, tw, plane, z0);
+    k_stepd_rows<N, T, RB><<<(N / RB) * nz, R1 * RB, 0, st>>>(P, ptr, ent, wts, cnt_inv, tw, plane, z0, nz);
     k_stepd_cols<N, T, CC><<<dim3(N / CC, nz), R1 * CC, 0, st>>>(plane, tw, vol, z0);
   }
 }
