@@ -35,7 +35,8 @@ def _run(cmd):
     return r.stdout
 
 
-SOURCES = ["cpra.hip", "inst_64.hip", "inst_128.hip", "inst_256.hip", "inst_512.hip", "inst_1024.hip"]
+SOURCES = ["cpra.hip", "inst_64.hip", "inst_128.hip", "inst_192.hip", "inst_256.hip", "inst_384.hip", "inst_512.hip",
+           "inst_1024.hip"]
 
 
 def build(verbose: bool = False, jobs: int | None = None) -> str:

@@ -36,25 +36,31 @@ int mode_of(int32_t algo) { return algo == CPRA_HIO ? 1 : algo == CPRA_RAAR ? 4 
 thread_local std::string g_create_error;
 
 
-bool size_supported(int N) { return N == 64 || N == 128 || N == 256 || N == 512 || N == 1024; }
+bool size_supported(int N) {
+  return N == 64 || N == 128 || N == 192 || N == 256 || N == 384 || N == 512 || N == 1024;
+}
 
 int col_tiles(int N) {
   switch (N) {
     case 64: return ColGeom<64>::TILES;
     case 128: return ColGeom<128>::TILES;
+    case 192: return ColGeom<192>::TILES;
     case 256: return ColGeom<256>::TILES;
+    case 384: return ColGeom<384>::TILES;
     case 512: return ColGeom<512>::TILES;
     default: return ColGeom<1024>::TILES;
   }
 }
 
-int stepd_chunk(int N) { return N >= 512 ? 32 : N; }
+int stepd_chunk(int N) { return N >= 384 ? 32 : N; }
 
 size_t mask_words_per_row(int N) {
   switch (N) {
     case 64: return RowGeom<64>::T * RowGeom<64>::MW;
     case 128: return RowGeom<128>::T * RowGeom<128>::MW;
+    case 192: return RowGeom<192>::T * RowGeom<192>::MW;
     case 256: return RowGeom<256>::T * RowGeom<256>::MW;
+    case 384: return RowGeom<384>::T * RowGeom<384>::MW;
     case 512: return RowGeom<512>::T * RowGeom<512>::MW;
     default: return RowGeom<1024>::T * RowGeom<1024>::MW;
   }
@@ -64,7 +70,9 @@ int tau_count(int N) {
   switch (N) {
     case 64: return RowGeom<64>::T;
     case 128: return RowGeom<128>::T;
+    case 192: return RowGeom<192>::T;
     case 256: return RowGeom<256>::T;
+    case 384: return RowGeom<384>::T;
     case 512: return RowGeom<512>::T;
     default: return RowGeom<1024>::T;
   }
@@ -74,7 +82,9 @@ int bit_to_t(int N, int tau, int b) {
   switch (N) {
     case 64: return mask_bit_t<64>(tau, b);
     case 128: return mask_bit_t<128>(tau, b);
+    case 192: return mask_bit_t<192>(tau, b);
     case 256: return mask_bit_t<256>(tau, b);
+    case 384: return mask_bit_t<384>(tau, b);
     case 512: return mask_bit_t<512>(tau, b);
     default: return mask_bit_t<1024>(tau, b);
   }
@@ -83,7 +93,7 @@ int bit_to_t(int N, int tau, int b) {
 cpra_status validate(const cpra_params* p, std::string& msg) {
   if (!p) { msg = "params is NULL"; return CPRA_ERR_ARG; }
   if (p->struct_size != sizeof(cpra_params)) { msg = "params.struct_size mismatch"; return CPRA_ERR_ARG; }
-  if (!size_supported(p->N)) { msg = "N must be 64, 128, 256, 512 or 1024"; return CPRA_ERR_UNSUPPORTED; }
+  if (!size_supported(p->N)) { msg = "N must be 64, 128, 192, 256, 384, 512 or 1024"; return CPRA_ERR_UNSUPPORTED; }
   if (p->Np < 1) { msg = "Np must be >= 1"; return CPRA_ERR_ARG; }
   if (p->n_taps != 0) {
     if (p->n_taps < 3 || p->n_taps % 2 == 0 || !p->taps) { msg = "n_taps must be 0 or an odd number >= 3 with taps set"; return CPRA_ERR_ARG; }
@@ -199,7 +209,9 @@ Ops ops_of(const cpra_params& p) {
   switch (p.N) {
     case 64: return ops_for_size<64>(p);
     case 128: return ops_for_size<128>(p);
+    case 192: return ops_for_size<192>(p);
     case 256: return ops_for_size<256>(p);
+    case 384: return ops_for_size<384>(p);
     case 512: return ops_for_size<512>(p);
     default: return ops_for_size<1024>(p);
   }

@@ -102,6 +102,17 @@ __device__ __forceinline__ void dft(C* x) {
     C a = x[0], b = x[1];
     x[0] = cadd(a, b);
     x[1] = csub(a, b);
+  } else if constexpr (R == 3) {
+    // w = exp(SIGN 2 pi i / 3) = -1/2 + SIGN i sqrt(3)/2
+    using T = decltype(C{}.x);
+    constexpr T h = (T)0.86602540378443864676372317075293618;   // sqrt(3)/2
+    const C a = x[0], b = x[1], c = x[2];
+    const C s = cadd(b, c);
+    const C m = mk<C>(a.x - (T)0.5 * s.x, a.y - (T)0.5 * s.y);
+    const C d = mul_i<SIGN>(csub(b, c));
+    x[0] = cadd(a, s);
+    x[1] = mk<C>(m.x + h * d.x, m.y + h * d.y);
+    x[2] = mk<C>(m.x - h * d.x, m.y - h * d.y);
   } else if constexpr (R % 4 == 0 && R >= 4 && (R == 4 || R >= 16)) {
     constexpr int Q = R / 4;
     C s0[Q], s1[Q], s2[Q], s3[Q];

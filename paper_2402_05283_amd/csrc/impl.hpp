@@ -289,7 +289,9 @@ template <int N> Ops ops_for_size(const cpra_params& p) {
 }
 extern template Ops ops_for_size<64>(const cpra_params&);
 extern template Ops ops_for_size<128>(const cpra_params&);
+extern template Ops ops_for_size<192>(const cpra_params&);
 extern template Ops ops_for_size<256>(const cpra_params&);
+extern template Ops ops_for_size<384>(const cpra_params&);
 extern template Ops ops_for_size<512>(const cpra_params&);
 extern template Ops ops_for_size<1024>(const cpra_params&);
 

@@ -35,6 +35,8 @@ template <int N> struct ColCfg;
 template <> struct ColCfg<64> { static constexpr int R1 = 8, R2 = 8, C = 16, S = 1; };
 template <> struct ColCfg<128> { static constexpr int R1 = 8, R2 = 16, C = 16, S = 1; };
 template <> struct ColCfg<256> { static constexpr int R1 = 16, R2 = 16, C = 16, S = 1; };
+template <> struct ColCfg<192> { static constexpr int R1 = 8, R2 = 24, C = 16, S = 1; };
+template <> struct ColCfg<384> { static constexpr int R1 = 8, R2 = 48, C = 16, S = 1; };
 template <> struct ColCfg<512> { static constexpr int R1 = 32, R2 = 16, C = 8, S = 2; };
 template <> struct ColCfg<1024> { static constexpr int R1 = 32, R2 = 32, C = 8, S = 1; };
 
@@ -48,6 +50,8 @@ template <int N> struct RowCfg;
 template <> struct RowCfg<64> { static constexpr int F1 = 4, F2 = 8, RPB = 32; };
 template <> struct RowCfg<128> { static constexpr int F1 = 8, F2 = 8, RPB = 16; };
 template <> struct RowCfg<256> { static constexpr int F1 = 8, F2 = 16, RPB = 16; };
+template <> struct RowCfg<192> { static constexpr int F1 = 4, F2 = 24, RPB = 32; };
+template <> struct RowCfg<384> { static constexpr int F1 = 8, F2 = 24, RPB = 16; };
 template <> struct RowCfg<512> { static constexpr int F1 = 16, F2 = 16, RPB = 16; };
 template <> struct RowCfg<1024> { static constexpr int F1 = 16, F2 = 32, RPB = 16; };
 
@@ -74,6 +78,16 @@ template <int N> struct ColGeom {
   static_assert(R1 * R2 == N && (N / 2) % C == 0, "column decomposition");
   static_assert(S == 1 ? (R2 % R1 == 0) : (S == 2 && R1 / 2 == R2), "step-2 ownership");
 };
+
+// x mod N into [0, N) (a mask for powers of two; sizes with a factor 3 take the remainder)
+template <int N> __host__ __device__ __forceinline__ int wrapN(int x) {
+  if constexpr ((N & (N - 1)) == 0) {
+    return x & (N - 1);
+  } else {
+    const int r = x % N;
+    return r < 0 ? r + N : r;
+  }
+}
 
 // Storage of an angle's N x N/2 complex planes (P, Pmid) and of its amplitude
 // pairs: chunks of CB packed columns, each chunk stored [z][CB] contiguously,
@@ -159,7 +173,7 @@ __global__ void __launch_bounds__(256) k_couple_taps(const cx<T>* __restrict__ P
     for (int q = 0; q < ntap; ++q) {
       const Tap tq = tp[q];
       const T* x = gin + ((size_t)tq.nb * N + z) * N;
-      acc += (T)tq.w * x[tq.mirror ? ((N - t) & (N - 1)) : t];
+      acc += (T)tq.w * x[tq.mirror ? (wrapN<N>(N - t)) : t];
     }
     gout[((size_t)n * N + z) * N + t] = acc;
   }
@@ -563,7 +577,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
           const auto pa = AmpIO<AP>::load(An + pix<N>(w, j), as);
           g[i] = Proj<T>::template two<ERR>(g[i], (T)pa.x, (T)pa.y, ((w + j) & 1) != 0, scale, err, 1.0);
         } else {
-          const int wm = (N - w) & (N - 1);
+          const int wm = wrapN<N>(N - w);
           const C Z = g[i], Zm = zl[wm];
           const C Ga = mk<C>((T)0.5 * (Z.x + Zm.x), (T)0.5 * (Z.y - Zm.y));
           const C Gb = mk<C>((T)0.5 * (Z.y + Zm.y), (T)0.5 * (Zm.x - Z.x));
@@ -589,7 +603,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
       constexpr int i = decltype(iv)::value;
       constexpr int q = i / R1, d = i % R1;
       const int w = a + R1 * q + R2 * d;
-      const int wm = (N - w) & (N - 1);
+      const int wm = wrapN<N>(N - w);
       C out;
       if (j != 0) {
         const auto pa = AmpIO<AP>::load(An + pix<N>(w, j), as);
@@ -778,7 +792,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
           const auto pa = AmpIO<AP>::load(An + pix<N>(w, j), as);
           g[k] = Proj<T>::template two<ERR>(g[k], (T)pa.x, (T)pa.y, ((w + j) & 1) != 0, scale, err, 1.0);
         } else {
-          const int wm = (N - w) & (N - 1);
+          const int wm = wrapN<N>(N - w);
           const C Z = g[k], Zm = zl[wm];
           const C Ga = mk<C>((T)0.5 * (Z.x + Zm.x), (T)0.5 * (Z.y - Zm.y));
           const C Gb = mk<C>((T)0.5 * (Z.y + Zm.y), (T)0.5 * (Zm.x - Z.x));
@@ -801,7 +815,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
     sfor<0, R2>([&](auto kv) CPRA_INLINE {
       constexpr int k = decltype(kv)::value;
       const int w = c + R2 * (k + R2 * sh);
-      const int wm = (N - w) & (N - 1);
+      const int wm = wrapN<N>(N - w);
       C out;
       if (j != 0) {
         const auto pa = AmpIO<AP>::load(An + pix<N>(w, j), as);
@@ -1034,9 +1048,9 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
             C gkv = gk[jj][m1];
             if constexpr (CPL) {
               C lv, rv;
-              if (cp.mirror_left) lv = mk<C>(gl[(N - 2 * m) & (N - 1)], gl[N - 1 - 2 * m]);
+              if (cp.mirror_left) lv = mk<C>(gl[wrapN<N>(N - 2 * m)], gl[N - 1 - 2 * m]);
               else lv = *reinterpret_cast<const C*>(gl + 2 * m);
-              if (cp.mirror_right) rv = mk<C>(gr[(N - 2 * m) & (N - 1)], gr[N - 1 - 2 * m]);
+              if (cp.mirror_right) rv = mk<C>(gr[wrapN<N>(N - 2 * m)], gr[N - 1 - 2 * m]);
               else rv = *reinterpret_cast<const C*>(gr + 2 * m);
               gkv = mk<C>(w0 * gkv.x + wl * lv.x + wr * rv.x, w0 * gkv.y + wl * lv.y + wr * rv.y);
             }

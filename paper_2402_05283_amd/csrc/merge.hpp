@@ -62,9 +62,9 @@ __global__ void __launch_bounds__(256) k_twin_dist(const T* __restrict__ g, cons
   double same = 0.0, inv = 0.0, unused = 0.0;
   for (int p = threadIdx.x; p < N * N; p += 256) {
     const int z = p / N, t = p % N;
-    const double ref = (double)xr[((z - rz) & (N - 1)) * N + ((t - rt) & (N - 1))];
-    const double a = (double)xj[((z - jz) & (N - 1)) * N + ((t - jt) & (N - 1))];
-    const double c = (double)xj[((N - z - jz) & (N - 1)) * N + ((N - t - jt) & (N - 1))];
+    const double ref = (double)xr[(wrapN<N>(z - rz)) * N + (wrapN<N>(t - rt))];
+    const double a = (double)xj[(wrapN<N>(z - jz)) * N + (wrapN<N>(t - jt))];
+    const double c = (double)xj[(wrapN<N>(N - z - jz)) * N + (wrapN<N>(N - t - jt))];
     same += (a - ref) * (a - ref);
     inv += (c - ref) * (c - ref);
   }
@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(256) k_merge_avg(const T* __restrict__ g, int 
       const T* x = g + ((size_t)keep[j] * npd + n) * N * N;
       const int sz = shift[2 * (j * npd + n)], st = shift[2 * (j * npd + n) + 1];
       const int zz = inv[j] ? N - z : z, tt = inv[j] ? N - t : t;
-      acc += (double)x[((zz - sz) & (N - 1)) * N + ((tt - st) & (N - 1))];
+      acc += (double)x[(wrapN<N>(zz - sz)) * N + (wrapN<N>(tt - st))];
     }
     out[((size_t)n * N + z) * N + t] = (T)(acc / (double)K);
   }

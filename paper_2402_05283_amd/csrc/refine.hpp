@@ -26,7 +26,7 @@ __device__ __forceinline__ void line_fft(cx<T>* line, cx<T>* scr, const cx<T>* _
   dft<R2, SIGN>(v);
 #pragma unroll
   for (int c = 0; c < R2; ++c) {
-    const C w = tw[(a * c) & (N - 1)];   // W_N^{ac} = exp(-2 pi i a c / N)
+    const C w = tw[wrapN<N>(a * c)];   // W_N^{ac} = exp(-2 pi i a c / N)
     scr[c * LS + a] = (c == 0 || a == 0) ? v[c] : (SIGN < 0 ? cmul(v[c], w) : cmulc(v[c], w));
   }
   __syncthreads();
@@ -76,11 +76,11 @@ __global__ void __launch_bounds__(256) k_ref_gather(const cx<T>* __restrict__ P,
                                                     const T* __restrict__ cnt_inv, cx<T>* __restrict__ Qh) {
   using C = cx<T>;
   const int ky = blockIdx.x, z = blockIdx.y;
-  const int mky = (N - ky) & (N - 1);
+  const int mky = wrapN<N>(N - ky);
   for (int kx = threadIdx.x; kx < N; kx += 256) {
     bool h1, h2;
     const C a = gather_cell<N, T>(P, ptr, ent, wts, cnt_inv, z, ky, kx, &h1);
-    const C b = gather_cell<N, T>(P, ptr, ent, wts, cnt_inv, z, mky, (N - kx) & (N - 1), &h2);
+    const C b = gather_cell<N, T>(P, ptr, ent, wts, cnt_inv, z, mky, wrapN<N>(N - kx), &h2);
     C out;
     if (h1 || h2) {
       const C av = h1 ? a : mk<C>((T)0, (T)0), bv = h2 ? b : mk<C>((T)0, (T)0);
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256) k_blur_z(T* __restrict__ buf, const T* __
   for (int i = threadIdx.x; i < N * CB; i += 256) {
     const int z = i / CB, c = i % CB;
     T acc = (T)0;
-    for (int d = -W; d <= W; ++d) acc += k[d + W] * col[((z - d) & (N - 1)) * CB + c];
+    for (int d = -W; d <= W; ++d) acc += k[d + W] * col[(wrapN<N>(z - d)) * CB + c];
     buf[((size_t)z * N + y) * N + x0 + c] = acc;
     m = fmax(m, (double)acc);
   }

@@ -20,7 +20,7 @@ __global__ void __launch_bounds__(256) k_blur_rows(const T* __restrict__ g, cons
   T* o = out + ((size_t)ai * N + z) * N;
   for (int t = threadIdx.x; t < N; t += 256) {
     T acc = (T)0;
-    for (int d = -W; d <= W; ++d) acc += k[d + W] * row[(t - d) & (N - 1)];
+    for (int d = -W; d <= W; ++d) acc += k[d + W] * row[wrapN<N>(t - d)];
     o[t] = acc;
   }
 }
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) k_blur_cols(T* __restrict__ buf, const T*
   for (int i = threadIdx.x; i < N * CB; i += 256) {
     const int z = i / CB, c = i % CB;
     T acc = (T)0;
-    for (int d = -W; d <= W; ++d) acc += k[d + W] * col[((z - d) & (N - 1)) * CB + c];
+    for (int d = -W; d <= W; ++d) acc += k[d + W] * col[(wrapN<N>(z - d)) * CB + c];
     x[(size_t)z * N + t0 + c] = acc;
     m = fmax(m, (double)acc);
   }

@@ -20,8 +20,17 @@ template <int N> struct StepdCfg;
 template <> struct StepdCfg<64> { static constexpr int R1 = 8, R2 = 8; };
 template <> struct StepdCfg<128> { static constexpr int R1 = 8, R2 = 16; };
 template <> struct StepdCfg<256> { static constexpr int R1 = 16, R2 = 16; };
+template <> struct StepdCfg<192> { static constexpr int R1 = 8, R2 = 24; };
+template <> struct StepdCfg<384> { static constexpr int R1 = 8, R2 = 48; };
 template <> struct StepdCfg<512> { static constexpr int R1 = 16, R2 = 32; };
 template <> struct StepdCfg<1024> { static constexpr int R1 = 32, R2 = 32; };
+
+// largest power-of-two count <= want whose LDS (per_line complex values each) fits 128 KiB
+template <int N, typename T> constexpr int stepd_lines(int want, size_t per_line) {
+  int k = want;
+  while (k > 1 && (size_t)k * per_line * sizeof(cx<T>) > 131072) k /= 2;
+  return k;
+}
 
 // S[z][u] of an angle from its packed half spectrum Pn (layout pix<N>)
 template <int N, typename T>
@@ -104,7 +113,7 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
   // inverse four-step along kx = a + R1 b -> x = c + R2 d
   dft<R2, +1>(v);
 #pragma unroll
-  for (int c = 0; c < R2; ++c) L0[c * LS + a] = (c == 0 || a == 0) ? v[c] : cmulc(v[c], tw[(a * c) & (N - 1)]);
+  for (int c = 0; c < R2; ++c) L0[c * LS + a] = (c == 0 || a == 0) ? v[c] : cmulc(v[c], tw[wrapN<N>(a * c)]);
   __syncthreads();
   C* out = plane + ((size_t)zi * N + ky) * N;
 #pragma unroll
@@ -139,7 +148,7 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* CC)
   dft<R2, +1>(v);
 #pragma unroll
   for (int c = 0; c < R2; ++c)
-    lds[c * LSTRIDE + a * CC + col] = (c == 0 || a == 0) ? v[c] : cmulc(v[c], tw[(a * c) & (N - 1)]);
+    lds[c * LSTRIDE + a * CC + col] = (c == 0 || a == 0) ? v[c] : cmulc(v[c], tw[wrapN<N>(a * c)]);
   __syncthreads();
   const T norm = (T)1 / ((T)N * (T)N);
   T* out = vol + (size_t)(z0 + zi) * N * N;
@@ -159,9 +168,10 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* CC)
 template <int N, typename T>
 void stepd_run(const cx<T>* P, const int* ptr, const int* ent, const T* wts, const T* cnt_inv, const cx<T>* tw,
                cx<T>* plane, int zc, T* vol, hipStream_t st) {
-  constexpr int R1 = StepdCfg<N>::R1;
-  constexpr int RB = (256 / R1) < N ? (256 / R1) : N;
-  constexpr int CC = (256 / R1) < N ? (256 / R1) : N;
+  constexpr int R1 = StepdCfg<N>::R1, R2 = StepdCfg<N>::R2;
+  // rows / columns per workgroup: up to 256 threads, LDS within 128 KiB
+  constexpr int RB = stepd_lines<N, T>(256 / R1 < N ? 256 / R1 : N, (size_t)R2 * (R1 + 1));
+  constexpr int CC = stepd_lines<N, T>(256 / R1 < N ? 256 / R1 : N, (size_t)R2 * R1);
   for (int z0 = 0; z0 < N; z0 += zc) {
     const int nz = (N - z0) < zc ? (N - z0) : zc;
     k_stepd_rows<N, T, RB><<<(N / RB) * nz, R1 * RB, 0, st>>>(P, ptr, ent, wts, cnt_inv, tw, plane, z0, nz);

@@ -52,7 +52,7 @@ def test_workspace_size_and_validation():
     assert e.value.status == -5 and "N must be" in str(e.value)
 
 
-@pytest.mark.parametrize("N,Np", [(16, 7), (64, 16), (256, 180), (512, 360)])
+@pytest.mark.parametrize("N,Np", [(16, 7), (64, 16), (192, 90), (256, 180), (512, 360)])
 def test_slice_cells_bit_exact_vs_oracle(N, Np):
     theta = np.pi * np.arange(Np) / Np
     kx, ky = cp.slice_cells(N, Np)

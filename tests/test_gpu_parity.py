@@ -26,7 +26,7 @@ def torch():
 
 
 @pytest.mark.parametrize("real", [F32, F64])
-@pytest.mark.parametrize("N", [64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("N", [64, 128, 192, 256, 384, 512, 1024])
 def test_initial_objects(torch, N, real):
     scan = make_scan(1, N=N, Np=5)
     banner(f"initial objects N={N} real={real}")
@@ -37,7 +37,7 @@ def test_initial_objects(torch, N, real):
 
 
 @pytest.mark.parametrize("real", [F32, F64])
-@pytest.mark.parametrize("N", [64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("N", [64, 128, 192, 256, 384, 512, 1024])
 def test_one_iteration(torch, N, real):
     """First iteration: coupling of W_0 (mirror seam), FFTs, projection, error, HIO."""
     scan = make_scan(1, N=N, Np=5)
@@ -204,7 +204,7 @@ def test_step_d_volume(torch, real):
 
 def test_step_d_larger_sizes(torch):
     from oracle import stepd as D
-    for N, Np in ((128, 9), (256, 7)):
+    for N, Np in ((128, 9), (192, 7), (256, 7)):
         scan = make_scan(1, N=N, Np=Np)
         banner(f"step D N={N} Np={Np}")
         plan, obj, _ = run_gpu(scan, [(2, HIO, 0.9)], real=F64, n_ei=2)
@@ -215,7 +215,7 @@ def test_step_d_larger_sizes(torch):
 
 
 @pytest.mark.parametrize("real", [F32, F64])
-@pytest.mark.parametrize("N,Np", [(512, 5), (1024, 3)])
+@pytest.mark.parametrize("N,Np", [(384, 5), (512, 5), (1024, 3)])
 def test_step_d_sampled_voxels(torch, N, Np, real):
     """Step D at N = 512 and 1024 in the benchmark's launch configuration, checked at sampled
     voxels that the oracle evaluates one by one from the definition."""
