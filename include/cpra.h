@@ -54,7 +54,8 @@ enum { CPRA_PTR_HOST = 0, CPRA_PTR_DEVICE = 1 };
 
 typedef struct {
   uint32_t struct_size;  /* = sizeof(cpra_params)                                     */
-  int32_t N;             /* map side; 64, 128, 256, 512 or 1024 (else UNSUPPORTED)      */
+  int32_t N;             /* map side; 64, 128, 192, 256, 384, 512 or 1024 (else        
+                            UNSUPPORTED)                                               */
   int32_t Np;            /* number of angles, >= 1                                      */
   const double* theta;   /* Np angles in radians (host, copied), or NULL: pi*n/Np       */
   double alpha[3];       /* Eq. 4 weights a_-1, a_0, a_+1; each >= 0, |sum - 1| <= 1e-12 */
