@@ -448,6 +448,63 @@ def variants(cp, torch, scan, I, S, args):
     return out
 
 
+def batched_scans(cp, torch, scan512, args):
+    """Config-3-like batch: 48 scans of uneven size (N drawn from {128, 192, 256, 384, 512}, N_p
+    from [90, 360], seeded), 300 HIO iterations each, advanced together through
+    cpra_iterate_batch (every plan on its own stream), against the same plans iterated one after
+    another.  Frames come from one synthetic scan per N (the bench scan for N = 512), each plan
+    taking a seeded subset of its angles and its own phase seed."""
+    from synth import make_scan
+    rng = np.random.default_rng(3)
+    sizes = rng.choice([128, 192, 256, 384, 512], size=args.batch_scans)
+    nps = rng.integers(90, 361, size=args.batch_scans)
+    src = {512: scan512}
+    for n in sorted(set(int(x) for x in sizes) - {512}):
+        print(f"[bench] batched: generating the N={n} source scan", file=sys.stderr, flush=True)
+        src[n] = make_scan(2 if n >= 256 else 1, N=n, Np=360)
+    dev = torch.device("cuda", 0)
+    data = {n: (torch.from_numpy(s["I"]).to(dev), torch.from_numpy(s["support"]).to(dev), s["theta"])
+            for n, s in src.items()}
+
+    def make_plans(streams):
+        plans = []
+        for i, (n, npp) in enumerate(zip(sizes, nps)):
+            n, npp = int(n), int(npp)
+            I, S, th = data[n]
+            idx = np.sort(rng_sub.choice(360, size=npp, replace=False))
+            it = torch.from_numpy(idx).to(dev)
+            p = cp.Plan(n, npp, theta=th[idx], n_ei=N_EI, seed=1000 + i, stream=streams[i] if streams else None)
+            p.submit(0, I.index_select(0, it).contiguous(), S.index_select(0, it).contiguous())
+            plans.append(p)
+        torch.cuda.synchronize()
+        return plans
+
+    iters = args.batch_iters
+    work = int(iters * nps.sum())
+    rng_sub = np.random.default_rng(4)
+    plans = make_plans(None)
+    t0 = time.perf_counter()
+    for p in plans:
+        p.iterate(iters, cp.HIO, BETA)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    del plans
+    rng_sub = np.random.default_rng(4)
+    streams = [torch.cuda.Stream() for _ in sizes]
+    plans = make_plans(streams)
+    t0 = time.perf_counter()
+    cp.iterate_batch(plans, iters, cp.HIO, BETA)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    del plans
+    torch.cuda.empty_cache()
+    return {"scans": int(args.batch_scans), "iterations": iters, "pattern_iterations": work,
+            "sizes": {int(n): int((sizes == n).sum()) for n in sorted(set(int(x) for x in sizes))},
+            "batched_s": round(t_bat, 3), "sequential_s": round(t_seq, 3),
+            "batched_pattern_iterations_per_s": round(work / t_bat, 1),
+            "sequential_pattern_iterations_per_s": round(work / t_seq, 1)}
+
+
 def quality_error_only(torch, obj, A_nat, den):
     err = []
     for c0 in range(0, obj.shape[0], 60):
@@ -469,6 +526,8 @@ def main():
     ap.add_argument("--serve-fps", type=float, default=20.0, help="frames per second per scan")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain per-angle comparison")
     ap.add_argument("--guesses", type=int, default=100, help="N_r of the paper-schedule leg (0: skip it)")
+    ap.add_argument("--batch-scans", type=int, default=48, help="scans of the uneven-size batch leg (0: skip)")
+    ap.add_argument("--batch-iters", type=int, default=300)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (the byte-counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -598,6 +657,9 @@ def main():
     if args.guesses > 0 and args.iters == ITERS and not args.amp16:
         print(f"[bench] paper schedule, {args.guesses} guesses", file=sys.stderr, flush=True)
         out["paper_schedule"] = paper_schedule(cp, torch, scan, I, S, args)
+    if args.batch_scans > 0 and args.iters == ITERS and not args.amp16:
+        print(f"[bench] batched: {args.batch_scans} scans of uneven size", file=sys.stderr, flush=True)
+        out["batched_uneven_scans"] = batched_scans(cp, torch, scan, args)
     if args.serve_scans > 0:
         out["latency_ms"] = serving_latency(cp, torch, scan, I, S, args)
         out["latency_ms"]["whole_scan_p50"] = round(float(np.percentile(lat, 50)) * 1e3, 2)
