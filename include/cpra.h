@@ -180,6 +180,17 @@ cpra_status cpra_sweep(cpra_plan_t plan, int32_t n_episodes, int32_t algo, doubl
 cpra_status cpra_merge(cpra_plan_t plan, int32_t n_best, int32_t* kept, int32_t* inverted);
 
 /*
+ * HIP graphs for the iteration (off by default): with enable != 0, whole
+ * episodes that start at a boundary (k mod n_ei == 0) in cpra_iterate
+ * without err_out and in cpra_iterate_batch are replayed from a captured
+ * graph of the episode's 2 n_ei launches (one graph per ping-pong parity,
+ * recaptured when the angle set, algo or beta changes).  Results are
+ * bit-identical to the launch-by-launch path; per-pass event timing is not
+ * recorded for graph episodes.  Saves launch overhead for small N.
+ */
+cpra_status cpra_set_graphs(cpra_plan_t plan, int32_t enable);
+
+/*
  * Several independent scans at once (the data-parallel dimension of steps B
  * and C over scans rather than angles): `count` distinct plans, possibly of
  * different N and Np, each advance n_iter iterations with the same algo and
@@ -218,8 +229,8 @@ cpra_status cpra_read_support(cpra_plan_t plan, uint8_t* out);
 /*
  * Current real-space iterate of every slot, n_guess x Np x N x N [r][n][z][t]
  * centred, float (F32 plans) or double (F64 plans), host or device.  At an
- * episode end this is the episode's estimate.  Host copies synchronise the
- * stream.
+ * episode end this is the episode's estimate; angles not submitted yet read
+ * as zero.  Host copies synchronise the stream.
  */
 cpra_status cpra_read_objects(cpra_plan_t plan, void* out, int32_t ptr_kind);
 

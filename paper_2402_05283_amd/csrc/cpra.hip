@@ -259,6 +259,7 @@ cpra_status upload_tables(cpra_plan_t pl) {
   // the host vectors are rewritten at the next boundary: make the copies complete first
   HIPCHK(pl, hipStreamSynchronize(pl->stream));
   pl->tables_dirty = false;
+  pl->table_version += 1;
   return CPRA_OK;
 }
 
@@ -312,6 +313,8 @@ cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t 
   ops.twiddles(pl);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemsetAsync(pl->ws + L.flags, 0, 256, pl->stream);
+  // angles not submitted yet read back as zero objects
+  if (e == hipSuccess) e = hipMemsetAsync(pl->ws + L.g0, 0, L.A2 - L.g0, pl->stream);
   // step-D tables (integer map built on the host in FP64)
   std::vector<int32_t> rp, ent;
   std::vector<double> wts;
@@ -441,6 +444,75 @@ static cpra_status step_once(cpra_plan_t pl, const Ops& ops, int32_t algo, doubl
   return CPRA_OK;
 }
 
+// Capture one episode (n_ei iterations from a boundary, starting with buffer `parity` current)
+// into pl->gexec[parity].  Kernels only: no copies or fills are recorded.  The capture runs on a
+// private stream; the graph is launched on the plan's stream.
+static cpra_status capture_episode(cpra_plan_t pl, const Ops& ops, int32_t algo, double beta, int parity) {
+  if (!pl->cap_stream) HIPCHK(pl, hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+  const hipStream_t keep_stream = pl->stream;
+  const bool keep_timing = pl->timing;
+  const int keep_cur = pl->cur;
+  pl->stream = pl->cap_stream;
+  pl->timing = false;
+  pl->cur = parity;
+  hipError_t e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
+  hipGraph_t g = nullptr;
+  if (e == hipSuccess) {
+    const int nact = (int)pl->alist_h.size();
+    for (int it = 0; it < pl->p.n_ei; ++it) {
+      const int mode = it == pl->p.n_ei - 1 ? 2 : mode_of(algo);
+      do_step(pl, ops, at<int>(pl, pl->L.alist), nact, it == 0, false, mode, beta, nullptr);
+      if (it == 0) pl->cur ^= 1;
+    }
+    e = hipStreamEndCapture(pl->cap_stream, &g);
+  }
+  pl->stream = keep_stream;
+  pl->timing = keep_timing;
+  pl->cur = keep_cur;
+  if (e != hipSuccess) return fail(pl, CPRA_ERR_DEVICE, "episode capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&pl->gexec[parity], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(pl, CPRA_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+  return CPRA_OK;
+}
+
+// One whole episode from a boundary (k mod n_ei == 0) through the captured graph of the current
+// parity; same arithmetic as n_ei calls of step_once.
+static cpra_status graph_episode(cpra_plan_t pl, const Ops& ops, int32_t algo, double beta) {
+  if (pl->present != pl->landed) {
+    pl->present = pl->landed;
+    pl->tables_dirty = true;
+  }
+  if (pl->tables_dirty) {
+    cpra_status st = upload_tables(pl);
+    if (st != CPRA_OK) return st;
+  }
+  if (pl->g_algo != algo || pl->g_beta != beta || pl->g_version != pl->table_version) {
+    pl->drop_graphs();
+    pl->g_algo = algo;
+    pl->g_beta = beta;
+    pl->g_version = pl->table_version;
+  }
+  if (!pl->gexec[pl->cur]) {
+    cpra_status st = capture_episode(pl, ops, algo, beta, pl->cur);
+    if (st != CPRA_OK) return st;
+  }
+  HIPCHK(pl, hipGraphLaunch(pl->gexec[pl->cur], pl->stream));
+  pl->cur ^= 1;
+  pl->k += pl->p.n_ei;
+  return CPRA_OK;
+}
+
+// n iterations of one plan without error history: whole episodes through graphs where possible
+static cpra_status advance(cpra_plan_t pl, const Ops& ops, int32_t algo, double beta, int32_t& n) {
+  if (pl->use_graphs && pl->k % pl->p.n_ei == 0 && n >= pl->p.n_ei) {
+    n -= pl->p.n_ei;
+    return graph_episode(pl, ops, algo, beta);
+  }
+  n -= 1;
+  return step_once(pl, ops, algo, beta);
+}
+
 cpra_status cpra_iterate_batch(cpra_plan_t* plans, int32_t count, int32_t n_iter, int32_t algo, double beta) {
   if (!plans) return fail(nullptr, CPRA_ERR_ARG, "plans is NULL");
   if (count < 0) return fail(nullptr, CPRA_ERR_ARG, "count < 0");
@@ -458,14 +530,20 @@ cpra_status cpra_iterate_batch(cpra_plan_t* plans, int32_t count, int32_t n_iter
     if (!any) return fail(pl, CPRA_ERR_STATE, "no angle has been submitted");
   }
   std::vector<Ops> ops(count);
+  std::vector<int32_t> left(count, n_iter);
   for (int i = 0; i < count; ++i) ops[i] = ops_of(plans[i]->p);
   cpra_status worst = CPRA_OK;
-  for (int it = 0; it < n_iter; ++it)
+  // round robin: each round advances every plan by one iteration, or by one episode when the
+  // plan replays captured episodes
+  for (bool more = n_iter > 0; more;) {
+    more = false;
     for (int i = 0; i < count; ++i) {
-      if (plans[i]->poisoned) continue;
-      const cpra_status st = step_once(plans[i], ops[i], algo, beta);
+      if (left[i] <= 0 || plans[i]->poisoned) continue;
+      const cpra_status st = advance(plans[i], ops[i], algo, beta, left[i]);
       if (st != CPRA_OK) worst = st;
+      more = more || left[i] > 0;
     }
+  }
   return worst;
 }
 
@@ -482,6 +560,14 @@ cpra_status cpra_iterate(cpra_plan_t pl, int32_t n_iter, int32_t algo, double be
     if (!any) return fail(pl, CPRA_ERR_STATE, "no angle has been submitted");
   }
   Ops ops = ops_of(pl->p);
+  if (!err_out && pl->use_graphs) {
+    int32_t left = n_iter;
+    while (left > 0) {
+      const cpra_status st = advance(pl, ops, algo, beta, left);
+      if (st != CPRA_OK) return st;
+    }
+    return CPRA_OK;
+  }
   const size_t Sl = (size_t)Np * pl->R;
   if (err_out)
     for (size_t i = 0; i < (size_t)n_iter * Sl; ++i) err_out[i] = NAN;
@@ -961,6 +1047,13 @@ const char* cpra_last_error(cpra_plan_t pl) { return pl ? pl->err.c_str() : g_cr
 cpra_status cpra_iteration_count(cpra_plan_t pl, int64_t* k) {
   if (!pl || !k) return CPRA_ERR_ARG;
   *k = pl->k;
+  return CPRA_OK;
+}
+
+cpra_status cpra_set_graphs(cpra_plan_t pl, int32_t enable) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  pl->use_graphs = enable != 0;
+  if (!pl->use_graphs) pl->drop_graphs();
   return CPRA_OK;
 }
 

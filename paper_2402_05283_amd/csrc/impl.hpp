@@ -55,7 +55,23 @@ struct cpra_plan_s {
     }
     return evpool[ev_used++];
   }
+  // HIP graphs of one episode (n_ei iterations from a boundary), one per parity of cur, valid for
+  // one angle set (table_version), algorithm and beta
+  bool use_graphs = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int g_algo = -1;
+  double g_beta = 0.0;
+  uint64_t g_version = 0, table_version = 1;
+  void drop_graphs() {
+    for (auto& g : gexec) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  }
   ~cpra_plan_s() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
   }
 };

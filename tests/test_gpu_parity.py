@@ -442,6 +442,45 @@ def test_precision_study_n512(torch):
     assert res[("hio1", cp.AMP_F16)] <= 2e-2 and res[("er10", cp.AMP_F16)] <= 2e-2
 
 
+@pytest.mark.parametrize("taps", [None, (0.05, 0.15, 0.6, 0.15, 0.05)])
+def test_graph_episodes_match_launches(torch, taps):
+    """Episodes replayed from captured HIP graphs equal the launch-by-launch path bit for bit: over
+    several replays of both parities with eager work and host reads in between, across a change
+    of algorithm, a mid-episode tail (eager), a new angle joining (recapture), and in a batch."""
+    import paper_2402_05283_amd as cp
+    scan = make_scan(1, Np=8)
+    banner(f"graph episodes taps={taps}")
+
+    def run(graphs):
+        p = cp.Plan(64, 8, theta=scan["theta"], n_ei=5, seed=scan["phase_seed"], taps=taps)
+        p.set_graphs(graphs)
+        p.submit(0, scan["I"][:6], scan["support"][:6])
+        snaps = []
+        p.iterate(15, cp.HIO, 0.9)                 # three episodes (both parities, replayed)
+        snaps.append(p.objects().cpu().numpy())
+        p.iterate(10, cp.ER, 0.0)                  # new algorithm: recapture
+        p.iterate(3, cp.HIO, 0.9)                  # tail, not a whole episode
+        p.iterate(2, cp.HIO, 0.9)
+        snaps.append(p.objects().cpu().numpy())
+        p.submit(6, scan["I"][6:], scan["support"][6:])   # the angle set grows: recapture
+        p.iterate(10, cp.HIO, 0.9)
+        snaps.append(p.objects().cpu().numpy())
+        return p, snaps
+
+    _, ref = run(False)
+    pg, got = run(True)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+    # batch with graphs against the launch path
+    p2, _ = run(True)
+    p3, _ = run(False)
+    cp.iterate_batch([pg, p2], 10, cp.HIO, 0.9)
+    p3.iterate(10, cp.HIO, 0.9)
+    torch.cuda.synchronize()
+    assert np.array_equal(pg.objects().cpu().numpy(), p3.objects().cpu().numpy())
+    assert np.array_equal(p2.objects().cpu().numpy(), p3.objects().cpu().numpy())
+
+
 def test_iterate_batch_matches_alone(torch):
     """cpra_iterate_batch: three scans of different N and Np, each on its own stream and at a
     different episode phase, advance together and end bit-identical to the same scans iterated
