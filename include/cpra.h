@@ -191,6 +191,20 @@ cpra_status cpra_merge(cpra_plan_t plan, int32_t n_best, int32_t* kept, int32_t*
 cpra_status cpra_set_graphs(cpra_plan_t plan, int32_t enable);
 
 /*
+ * Launch order inside an episode.  Between two coupling boundaries every
+ * slot iterates on its own, so the n_ei - 1 iterations after a boundary may
+ * run chunk by chunk: the listed slots are cut into chunks of `slots`, and
+ * each chunk runs all of those iterations (column and row pass per
+ * iteration) before the next chunk starts.  A chunk's planes then stay in
+ * the last-level cache between passes.  The boundary iteration always runs
+ * over all slots (Eq. 4 reads the neighbours' previous episode).  Results
+ * are bit-identical for any chunk size.  slots = 0 (the default) or
+ * slots >= listed slots: every launch covers all slots.  ERR_ARG if
+ * slots < 0.
+ */
+cpra_status cpra_set_chunk(cpra_plan_t plan, int32_t slots);
+
+/*
  * Several independent scans at once (the data-parallel dimension of steps B
  * and C over scans rather than angles): `count` distinct plans, possibly of
  * different N and Np, each advance n_iter iterations with the same algo and

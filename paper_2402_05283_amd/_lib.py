@@ -30,7 +30,7 @@ EXPORTED = [
     "cpra_assemble_volume", "cpra_destroy", "cpra_last_error", "cpra_iteration_count", "cpra_slice_cells",
     "cpra_coupling_table", "cpra_set_kernel_timing", "cpra_kernel_timing", "cpra_load_objects",
     "cpra_iterate_batch", "cpra_prereconstruct", "cpra_sweep", "cpra_merge", "cpra_shrinkwrap",
-    "cpra_read_support", "cpra_refine_workspace_size", "cpra_refine_volume", "cpra_set_graphs",
+    "cpra_read_support", "cpra_refine_workspace_size", "cpra_refine_volume", "cpra_set_graphs", "cpra_set_chunk",
 ]
 
 
@@ -87,6 +87,7 @@ def load():
     lib.cpra_shrinkwrap.argtypes = [c.c_void_p, c.c_double, c.c_double]
     lib.cpra_read_support.argtypes = [c.c_void_p, c.c_void_p]
     lib.cpra_set_graphs.argtypes = [c.c_void_p, c.c_int32]
+    lib.cpra_set_chunk.argtypes = [c.c_void_p, c.c_int32]
     lib.cpra_refine_workspace_size.argtypes = [P(Params), P(c.c_size_t)]
     lib.cpra_refine_volume.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_double, c.c_double, c.c_void_p,
                                        c.c_size_t, c.c_void_p]
@@ -335,6 +336,10 @@ class Plan:
     def set_graphs(self, enable=True):
         """Replay whole episodes from captured HIP graphs (see cpra_set_graphs)."""
         _check(load().cpra_set_graphs(self.handle, int(bool(enable))), self.handle)
+
+    def set_chunk(self, slots):
+        """Chunk-major order inside episodes, `slots` per chunk; 0 turns it off (cpra_set_chunk)."""
+        _check(load().cpra_set_chunk(self.handle, int(slots)), self.handle)
 
     def set_kernel_timing(self, enable=True):
         _check(load().cpra_set_kernel_timing(self.handle, int(bool(enable))), self.handle)

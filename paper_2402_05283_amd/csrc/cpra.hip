@@ -423,17 +423,51 @@ static void do_step(cpra_plan_t pl, const Ops& ops, const int* al, int nact, boo
   }
 }
 
-// one iteration of one plan with no error history: episode bookkeeping, then the two passes
-static cpra_status step_once(cpra_plan_t pl, const Ops& ops, int32_t algo, double beta) {
-  const bool boundary = (pl->k % pl->p.n_ei) == 0;
-  if (boundary && pl->present != pl->landed) {
+// episode bookkeeping before an iteration: the angle set changes only at a boundary
+static cpra_status refresh_tables(cpra_plan_t pl) {
+  if ((pl->k % pl->p.n_ei) == 0 && pl->present != pl->landed) {
     pl->present = pl->landed;
     pl->tables_dirty = true;
   }
-  if (pl->tables_dirty) {
-    cpra_status st = upload_tables(pl);
-    if (st != CPRA_OK) return st;
+  return pl->tables_dirty ? upload_tables(pl) : CPRA_OK;
+}
+
+// m iterations after an episode's boundary, the first of them at position j0 (>= 1) of the
+// episode.  Between boundaries the slots do not interact, so the order is chunk-major: each
+// chunk of pl->chunk listed slots runs all m iterations before the next chunk starts, which keeps
+// a chunk's planes in the last-level cache from one pass to the next.  Same arithmetic as m
+// iterations over all slots.
+static void run_inner(cpra_plan_t pl, const Ops& ops, int32_t algo, double beta, int j0, int m) {
+  const int nact = (int)pl->alist_h.size();
+  const int ch = pl->chunk > 0 && pl->chunk < nact ? pl->chunk : nact;
+  const int* al = at<int>(pl, pl->L.alist);
+  for (int c0 = 0; c0 < nact; c0 += ch) {
+    const int cn = nact - c0 < ch ? nact - c0 : ch;
+    for (int i = 0; i < m; ++i) {
+      const int mode = (j0 + i + 1) % pl->p.n_ei == 0 ? 2 : mode_of(algo);
+      do_step(pl, ops, al + c0, cn, false, false, mode, beta, nullptr);
+    }
   }
+}
+
+// the rest of the current episode, at most n iterations, from a position j0 >= 1
+static cpra_status episode_rest(cpra_plan_t pl, const Ops& ops, int32_t algo, double beta, int32_t& n) {
+  cpra_status st = refresh_tables(pl);
+  if (st != CPRA_OK) return st;
+  const int j0 = (int)(pl->k % pl->p.n_ei);
+  const int m = pl->p.n_ei - j0 < n ? pl->p.n_ei - j0 : n;
+  run_inner(pl, ops, algo, beta, j0, m);
+  LAUNCHCHK(pl);
+  pl->k += m;
+  n -= m;
+  return CPRA_OK;
+}
+
+// one iteration of one plan with no error history: episode bookkeeping, then the two passes
+static cpra_status step_once(cpra_plan_t pl, const Ops& ops, int32_t algo, double beta) {
+  const bool boundary = (pl->k % pl->p.n_ei) == 0;
+  cpra_status st = refresh_tables(pl);
+  if (st != CPRA_OK) return st;
   const int nact = (int)pl->alist_h.size();
   const bool estimate = ((pl->k + 1) % pl->p.n_ei) == 0;
   const int mode = estimate ? 2 : mode_of(algo);
@@ -459,11 +493,10 @@ static cpra_status capture_episode(cpra_plan_t pl, const Ops& ops, int32_t algo,
   hipGraph_t g = nullptr;
   if (e == hipSuccess) {
     const int nact = (int)pl->alist_h.size();
-    for (int it = 0; it < pl->p.n_ei; ++it) {
-      const int mode = it == pl->p.n_ei - 1 ? 2 : mode_of(algo);
-      do_step(pl, ops, at<int>(pl, pl->L.alist), nact, it == 0, false, mode, beta, nullptr);
-      if (it == 0) pl->cur ^= 1;
-    }
+    do_step(pl, ops, at<int>(pl, pl->L.alist), nact, true, false, pl->p.n_ei == 1 ? 2 : mode_of(algo), beta,
+            nullptr);
+    pl->cur ^= 1;
+    if (pl->p.n_ei > 1) run_inner(pl, ops, algo, beta, 1, pl->p.n_ei - 1);
     e = hipStreamEndCapture(pl->cap_stream, &g);
   }
   pl->stream = keep_stream;
@@ -479,14 +512,8 @@ static cpra_status capture_episode(cpra_plan_t pl, const Ops& ops, int32_t algo,
 // One whole episode from a boundary (k mod n_ei == 0) through the captured graph of the current
 // parity; same arithmetic as n_ei calls of step_once.
 static cpra_status graph_episode(cpra_plan_t pl, const Ops& ops, int32_t algo, double beta) {
-  if (pl->present != pl->landed) {
-    pl->present = pl->landed;
-    pl->tables_dirty = true;
-  }
-  if (pl->tables_dirty) {
-    cpra_status st = upload_tables(pl);
-    if (st != CPRA_OK) return st;
-  }
+  cpra_status st0 = refresh_tables(pl);
+  if (st0 != CPRA_OK) return st0;
   if (pl->g_algo != algo || pl->g_beta != beta || pl->g_version != pl->table_version) {
     pl->drop_graphs();
     pl->g_algo = algo;
@@ -503,9 +530,11 @@ static cpra_status graph_episode(cpra_plan_t pl, const Ops& ops, int32_t algo, d
   return CPRA_OK;
 }
 
-// n iterations of one plan without error history: whole episodes through graphs where possible
+// advance one plan without error history by a boundary iteration, by the rest of an episode, or
+// by a whole episode through its graph, taking at most n iterations
 static cpra_status advance(cpra_plan_t pl, const Ops& ops, int32_t algo, double beta, int32_t& n) {
-  if (pl->use_graphs && pl->k % pl->p.n_ei == 0 && n >= pl->p.n_ei) {
+  if (pl->k % pl->p.n_ei != 0) return episode_rest(pl, ops, algo, beta, n);
+  if (pl->use_graphs && n >= pl->p.n_ei) {
     n -= pl->p.n_ei;
     return graph_episode(pl, ops, algo, beta);
   }
@@ -533,8 +562,8 @@ cpra_status cpra_iterate_batch(cpra_plan_t* plans, int32_t count, int32_t n_iter
   std::vector<int32_t> left(count, n_iter);
   for (int i = 0; i < count; ++i) ops[i] = ops_of(plans[i]->p);
   cpra_status worst = CPRA_OK;
-  // round robin: each round advances every plan by one iteration, or by one episode when the
-  // plan replays captured episodes
+  // round robin: each round advances every plan by its boundary iteration, by the rest of its
+  // episode, or by a whole episode when the plan replays captured episodes
   for (bool more = n_iter > 0; more;) {
     more = false;
     for (int i = 0; i < count; ++i) {
@@ -560,7 +589,7 @@ cpra_status cpra_iterate(cpra_plan_t pl, int32_t n_iter, int32_t algo, double be
     if (!any) return fail(pl, CPRA_ERR_STATE, "no angle has been submitted");
   }
   Ops ops = ops_of(pl->p);
-  if (!err_out && pl->use_graphs) {
+  if (!err_out) {
     int32_t left = n_iter;
     while (left > 0) {
       const cpra_status st = advance(pl, ops, algo, beta, left);
@@ -1054,6 +1083,14 @@ cpra_status cpra_set_graphs(cpra_plan_t pl, int32_t enable) {
   if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
   pl->use_graphs = enable != 0;
   if (!pl->use_graphs) pl->drop_graphs();
+  return CPRA_OK;
+}
+
+cpra_status cpra_set_chunk(cpra_plan_t pl, int32_t slots) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  if (slots < 0) return fail(pl, CPRA_ERR_ARG, "slots < 0");
+  pl->chunk = slots;
+  pl->drop_graphs();
   return CPRA_OK;
 }
 

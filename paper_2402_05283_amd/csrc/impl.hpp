@@ -58,6 +58,8 @@ struct cpra_plan_s {
   // HIP graphs of one episode (n_ei iterations from a boundary), one per parity of cur, valid for
   // one angle set (table_version), algorithm and beta
   bool use_graphs = false;
+  // slots per chunk of the chunk-major order inside an episode (0: all slots in every launch)
+  int chunk = 0;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int g_algo = -1;

@@ -481,6 +481,37 @@ def test_graph_episodes_match_launches(torch, taps):
     assert np.array_equal(p2.objects().cpu().numpy(), p3.objects().cpu().numpy())
 
 
+@pytest.mark.parametrize("taps", [None, (0.05, 0.15, 0.6, 0.15, 0.05)])
+def test_chunk_major_order_matches(torch, taps):
+    """Chunk-major order inside episodes (any chunk size, with and without graphs, with two guesses
+    and mid-episode tails) equals every launch covering all slots, bit for bit; so does the
+    per-iteration path that records the error history."""
+    import paper_2402_05283_amd as cp
+    scan = make_scan(1, Np=8)
+    banner(f"chunk-major order taps={taps}")
+
+    def run(chunk, graphs=False, errors=False):
+        p = cp.Plan(64, 8, theta=scan["theta"], n_ei=5, seed=scan["phase_seed"], taps=taps, n_guess=2)
+        p.set_chunk(chunk)
+        p.set_graphs(graphs)
+        p.submit(0, scan["I"][:7], scan["support"][:7])
+        for n, algo, beta in [(7, cp.HIO, 0.9), (1, cp.HIO, 0.9), (4, cp.ER, 0.0), (8, cp.RAAR, 0.8)]:
+            if errors:
+                p.iterate(n, algo, beta, errors=True)
+            else:
+                p.iterate(n, algo, beta)
+        p.submit(7, scan["I"][7:], scan["support"][7:])
+        p.iterate(10, cp.HIO, 0.9)
+        torch.cuda.synchronize()
+        return p.objects().cpu().numpy()
+
+    ref = run(0)
+    assert np.array_equal(run(0, errors=True), ref)
+    for chunk in (1, 3, 5, 16):
+        assert np.array_equal(run(chunk), ref), chunk
+    assert np.array_equal(run(3, graphs=True), ref)
+
+
 def test_iterate_batch_matches_alone(torch):
     """cpra_iterate_batch: three scans of different N and Np, each on its own stream and at a
     different episode phase, advance together and end bit-identical to the same scans iterated
