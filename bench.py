@@ -200,7 +200,7 @@ def summarize_trace(trace_dir, bench_json, cmd):
              "Command (repo root, one MI355X):", "", f"    {cmd}", "",
              f"Each step: plan set-up, submit of 360 angles (prep + initial objects), {b['config']['iterations']} "
              f"HIO iterations (coupling every {b['config']['n_ei']}), step D into a 512^3 volume.  "
-             f"Only the headline legs run (no comparison, schedule or serving legs).  "
+             f"Only the headline legs run (no comparison, schedule, batch or serving legs).  "
              f"bench.py in the same run: value {b['value']:.0f} pattern-iterations/s, {b['ms_per_step']:.1f} ms "
              f"per step; HIP-event mean launch time k_col {ev.get('k_col', 0) * 1e3:.1f} us, "
              f"k_row {ev.get('k_row', 0) * 1e3:.1f} us.", "",
@@ -537,7 +537,7 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         cmd = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace -o run "
-               "-- python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-compare --guesses 0 --serve-scans 0 "
+               "-- python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-compare --guesses 0 --serve-scans 0 --batch-scans 0 "
                "> gpurun_out/trace_bench.json")
         print(summarize_trace(*args.summarize_trace, cmd), end="")
         return
