@@ -181,6 +181,56 @@ __global__ void __launch_bounds__(256) k_couple_taps(const cx<T>* __restrict__ P
 }
 
 // ---------------------------------------------------------------- amplitudes
+// Plane stores and loads with an optional non-temporal cache hint.  Per size, which plane
+// traffic takes the hint: the planes are streamed once per pass, and whether the hint pays was
+// measured per size at 360 angles (it depends on how much of a pass's planes the last-level
+// cache holds, and on the store pattern: at N = 192 hinted row stores double the row pass).
+// Loads of the column pass's P and amplitudes and of the row pass's Pmid take no hint: the two
+// workgroups that share each cache line find the second half in L2.
+template <int N> struct NtPolicy {
+  static constexpr bool col_store = (N == 384 || N >= 512);   // column pass: Pmid stores
+  static constexpr bool row_store = (N == 256 || N >= 512);   // row pass: g and P stores
+  static constexpr bool row_gload = (N == 256 || N >= 512);   // row pass: loads of the iterate g
+};
+typedef float cpra_f2v __attribute__((ext_vector_type(2)));
+typedef double cpra_d2v __attribute__((ext_vector_type(2)));
+template <bool NT>
+__device__ __forceinline__ void st_plane(float2* p, float2 v) {
+  if constexpr (NT) {
+    cpra_f2v w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<cpra_f2v*>(p));
+  } else {
+    *p = v;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ void st_plane(double2* p, double2 v) {
+  if constexpr (NT) {
+    cpra_d2v w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<cpra_d2v*>(p));
+  } else {
+    *p = v;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ float2 ld_plane(const float2* p) {
+  if constexpr (NT) {
+    const cpra_f2v w = __builtin_nontemporal_load(reinterpret_cast<const cpra_f2v*>(p));
+    return make_float2(w.x, w.y);
+  } else {
+    return *p;
+  }
+}
+template <bool NT>
+__device__ __forceinline__ double2 ld_plane(const double2* p) {
+  if constexpr (NT) {
+    const cpra_d2v w = __builtin_nontemporal_load(reinterpret_cast<const cpra_d2v*>(p));
+    return make_double2(w.x, w.y);
+  } else {
+    return *p;
+  }
+}
+
 template <typename AP> struct AmpIO;
 template <> struct AmpIO<float2> {
   using real = float;
@@ -656,7 +706,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
     C* Mn = Pmid + (size_t)n * plane;
     sfor<0, R2>([&](auto bv) CPRA_INLINE {
       constexpr int b = decltype(bv)::value;
-      Mn[pix<N>(a + R1 * b, j)] = v[b];
+      st_plane<NtPolicy<N>::col_store>(Mn + pix<N>(a + R1 * b, j), v[b]);
     });
   }
   if constexpr (MODE == 0 && ERR) {
@@ -872,7 +922,7 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
     C* Mn = Pmid + (size_t)n * plane;
     sfor<0, R2>([&](auto bv) CPRA_INLINE {
       constexpr int b = decltype(bv)::value;
-      Mn[pix<N>(a + R1 * b, j)] = v[b];
+      st_plane<NtPolicy<N>::col_store>(Mn + pix<N>(a + R1 * b, j), v[b]);
     });
   }
   if constexpr (MODE == 0 && ERR) {
@@ -951,7 +1001,7 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
         constexpr int jj = decltype(jv)::value;
         sfor<0, F1>([&](auto mv) CPRA_INLINE {
           constexpr int m1 = decltype(mv)::value;
-          gk[jj][m1] = *reinterpret_cast<const C*>(gin + rowr + 2 * (tau + TT * jj + F2 * m1));
+          gk[jj][m1] = ld_plane<NtPolicy<N>::row_gload>(reinterpret_cast<const C*>(gin + rowr + 2 * (tau + TT * jj + F2 * m1)));
         });
       });
     }
@@ -1066,7 +1116,7 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
             }
           }
         }
-        *reinterpret_cast<C*>(gout + rowr + 2 * m) = out;
+        st_plane<NtPolicy<N>::row_store>(reinterpret_cast<C*>(gout + rowr + 2 * m), out);
         sp[jj][m1] = out;
       });
     });
@@ -1112,7 +1162,7 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
         const C Fe = mk<C>((T)0.5 * (Z.x + Zp.x), (T)0.5 * (Z.y - Zp.y));
         const C Fo = mk<C>((T)0.5 * (Z.y + Zp.y), (T)0.5 * (Zp.x - Z.x));
         const C o = cadd(Fe, cmul(Fo, tpair[decltype(hh)::value]));
-        P[pbase + pix<N>(z, tau + F1 * k2)] = k0 ? mk<C>(Z.x + Z.y, Z.x - Z.y) : o;
+        st_plane<NtPolicy<N>::row_store>(P + pbase + pix<N>(z, tau + F1 * k2), k0 ? mk<C>(Z.x + Z.y, Z.x - Z.y) : o);
       });
     });
   }
