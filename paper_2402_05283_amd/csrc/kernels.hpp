@@ -1020,15 +1020,18 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
     // ---- load Pmid class tau, C2R pre-processing:
     //   X'[k] = (a + b) + i (a - b) e^{+2 pi i k/N},  a = T[k], b = conj T[L-k]
     // (k = 0: a, b = the packed real DC and Nyquist values)
-    // the partner T[L-k] of k = tau + F1 k2 is read straight from memory: class
-    // (F1 - tau) at index F2-1-k2, or for class 0 its own index (F2 - k2) mod F2
-    // (same cache lines as this wave's own loads)
-    const int pcls = (F1 - tau) & (F1 - 1);
+    // the partner T[L-k] of k = tau + F1 k2 is class (F1 - tau)'s value at index
+    // F2-1-k2, taken from that lane by DPP, or for class 0 its own value at index
+    // (F2 - k2) mod F2
     C pv[F2];
     sfor<0, F2>([&](auto kk) CPRA_INLINE {
       constexpr int k2 = decltype(kk)::value;
       x[k2] = Pmid[pbase + pix<N>(z, tau + F1 * k2)];
-      pv[k2] = Pmid[pbase + pix<N>(z, pcls + F1 * (t0 ? (F2 - k2) % F2 : F2 - 1 - k2))];
+    });
+    sfor<0, F2>([&](auto kk) CPRA_INLINE {
+      constexpr int k2 = decltype(kk)::value;
+      const C other = partner_c<F1>(x[F2 - 1 - k2], plane_lane);
+      pv[k2] = t0 ? x[(F2 - k2) % F2] : other;
     });
     const C* tp = tw + TL::RPP + tau * F2;             // W_N^{k1 + F1 k2}
     sfor<0, F2 / 2>([&](auto kk) CPRA_INLINE {
