@@ -269,7 +269,11 @@ cpra_status cpra_load_objects(cpra_plan_t plan, const void* objects, int32_t ptr
  * the 3D inverse transform: N x N x N [z][y][x] centred, float (F32 plans)
  * or double (F64 plans), device memory.  Computed z-plane by z-plane (the
  * 3D transform factorises into the row spectra already held per angle), so
- * no N^3 complex grid is formed.  ERR_STATE unless k mod n_ei == 0 and k > 0.
+ * no N^3 complex grid is formed.  The first step-D call of a plan (this or
+ * cpra_refine_volume) builds the insertion tables on the host and uploads
+ * them on the stream (the host copy may wait for the stream's earlier
+ * work); the kernels are queued asynchronously.  ERR_STATE unless
+ * k mod n_ei == 0 and k > 0.
  */
 cpra_status cpra_assemble_volume(cpra_plan_t plan, void* d_volume);
 

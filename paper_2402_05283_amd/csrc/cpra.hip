@@ -315,36 +315,6 @@ cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t 
   if (e == hipSuccess) e = hipMemsetAsync(pl->ws + L.flags, 0, 256, pl->stream);
   // angles not submitted yet read back as zero objects
   if (e == hipSuccess) e = hipMemsetAsync(pl->ws + L.g0, 0, L.A2 - L.g0, pl->stream);
-  // step-D tables (integer map built on the host in FP64)
-  std::vector<int32_t> rp, ent;
-  std::vector<double> wts;
-  const bool bil = params->insertion == CPRA_INSERT_BILINEAR;
-  if (bil) cpra_host::insertion_csr_bilinear(params->N, params->Np, pl->theta.data(), rp, ent, wts);
-  else cpra_host::insertion_csr(params->N, params->Np, pl->theta.data(), rp, ent);
-  const size_t NN = (size_t)params->N * params->N;
-  if (e == hipSuccess) e = hipMemcpyAsync(pl->ws + L.csr_ptr, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, pl->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(pl->ws + L.csr_ent, ent.data(), ent.size() * 4, hipMemcpyHostToDevice, pl->stream);
-  std::vector<float> wts_f(wts.begin(), wts.end());
-  if (bil && e == hipSuccess) {
-    if (params->real_type == CPRA_REAL_F64)
-      e = hipMemcpyAsync(pl->ws + L.csr_w, wts.data(), wts.size() * 8, hipMemcpyHostToDevice, pl->stream);
-    else
-      e = hipMemcpyAsync(pl->ws + L.csr_w, wts_f.data(), wts_f.size() * 4, hipMemcpyHostToDevice, pl->stream);
-  }
-  std::vector<double> inv_d(NN);
-  std::vector<float> inv_f(NN);
-  for (size_t c = 0; c < NN; ++c) {
-    double tot = 0.0;   // entry count, or the sum of the bilinear weights (in entry order)
-    for (int i = rp[c]; i < rp[c + 1]; ++i) tot += bil ? wts[i] : 1.0;
-    inv_d[c] = tot > 0.0 ? 1.0 / tot : 0.0;
-    inv_f[c] = (float)inv_d[c];
-  }
-  if (e == hipSuccess) {
-    if (params->real_type == CPRA_REAL_F64)
-      e = hipMemcpyAsync(pl->ws + L.cnt_inv, inv_d.data(), NN * 8, hipMemcpyHostToDevice, pl->stream);
-    else
-      e = hipMemcpyAsync(pl->ws + L.cnt_inv, inv_f.data(), NN * 4, hipMemcpyHostToDevice, pl->stream);
-  }
   if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
   if (e != hipSuccess) {
     g_create_error = std::string("plan setup: ") + hipGetErrorString(e);
@@ -352,6 +322,43 @@ cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t 
     return CPRA_ERR_DEVICE;
   }
   *out = pl;
+  return CPRA_OK;
+}
+
+// Step-D tables: the integer cell map of the Fourier-slice insertion (built on the host in FP64),
+// the bilinear weights, and the inverse count (or weight sum) per cell.  Built at the first step-D
+// call rather than at plan creation, so that this host work overlaps the iterations already
+// queued on the stream; the uploads are ordered on the stream before step D's kernels.
+static cpra_status ensure_stepd_tables(cpra_plan_t pl) {
+  if (pl->stepd_ready) return CPRA_OK;
+  const cpra_params& p = pl->p;
+  const bool bil = p.insertion == CPRA_INSERT_BILINEAR;
+  const bool f64 = p.real_type == CPRA_REAL_F64;
+  std::vector<int32_t>& rp = pl->csr_rp;
+  std::vector<int32_t>& ent = pl->csr_ent;
+  std::vector<double>& wts = pl->csr_wd;
+  if (bil) cpra_host::insertion_csr_bilinear(p.N, p.Np, pl->theta.data(), rp, ent, wts);
+  else cpra_host::insertion_csr(p.N, p.Np, pl->theta.data(), rp, ent);
+  const size_t NN = (size_t)p.N * p.N;
+  pl->csr_wf.assign(wts.begin(), wts.end());
+  pl->inv_d.resize(NN);
+  pl->inv_f.resize(NN);
+  for (size_t c = 0; c < NN; ++c) {
+    double tot = 0.0;   // entry count, or the sum of the bilinear weights (in entry order)
+    for (int i = rp[c]; i < rp[c + 1]; ++i) tot += bil ? wts[i] : 1.0;
+    pl->inv_d[c] = tot > 0.0 ? 1.0 / tot : 0.0;
+    pl->inv_f[c] = (float)pl->inv_d[c];
+  }
+  const Layout& L = pl->L;
+  HIPCHK(pl, hipMemcpyAsync(pl->ws + L.csr_ptr, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, pl->stream));
+  HIPCHK(pl, hipMemcpyAsync(pl->ws + L.csr_ent, ent.data(), ent.size() * 4, hipMemcpyHostToDevice, pl->stream));
+  if (bil) {
+    if (f64) HIPCHK(pl, hipMemcpyAsync(pl->ws + L.csr_w, wts.data(), wts.size() * 8, hipMemcpyHostToDevice, pl->stream));
+    else HIPCHK(pl, hipMemcpyAsync(pl->ws + L.csr_w, pl->csr_wf.data(), wts.size() * 4, hipMemcpyHostToDevice, pl->stream));
+  }
+  if (f64) HIPCHK(pl, hipMemcpyAsync(pl->ws + L.cnt_inv, pl->inv_d.data(), NN * 8, hipMemcpyHostToDevice, pl->stream));
+  else HIPCHK(pl, hipMemcpyAsync(pl->ws + L.cnt_inv, pl->inv_f.data(), NN * 4, hipMemcpyHostToDevice, pl->stream));
+  pl->stepd_ready = true;
   return CPRA_OK;
 }
 
@@ -940,6 +947,10 @@ cpra_status cpra_refine_volume(cpra_plan_t pl, int32_t n_iter, int32_t shrink_ev
     return fail(pl, CPRA_ERR_OOM, "refinement workspace has %zu bytes, needs %zu", work_bytes, RL.total);
   if (pl->k == 0 || pl->k % pl->p.n_ei != 0)
     return fail(pl, CPRA_ERR_STATE, "the refinement starts from step D at an episode end (k=%lld)", (long long)pl->k);
+  {
+    cpra_status st = ensure_stepd_tables(pl);
+    if (st != CPRA_OK) return st;
+  }
   char* w = reinterpret_cast<char*>(work);
   // present data angles and their (sin, cos); then 0 .. N-1 (the planes as slots for the blur)
   std::vector<int32_t> list;
@@ -1060,6 +1071,8 @@ cpra_status cpra_assemble_volume(cpra_plan_t pl, void* d_volume) {
   if (!d_volume) return fail(pl, CPRA_ERR_ARG, "d_volume is NULL");
   if (pl->k == 0 || pl->k % pl->p.n_ei != 0)
     return fail(pl, CPRA_ERR_STATE, "step D needs an episode end (k=%lld, n_ei=%d)", (long long)pl->k, pl->p.n_ei);
+  cpra_status st = ensure_stepd_tables(pl);
+  if (st != CPRA_OK) return st;
   Ops ops = ops_of(pl->p);
   ops.assemble(pl, d_volume);
   LAUNCHCHK(pl);

@@ -60,6 +60,12 @@ struct cpra_plan_s {
   bool use_graphs = false;
   // slots per chunk of the chunk-major order inside an episode (0: all slots in every launch)
   int chunk = 0;
+  // step-D insertion tables, built on the host at the first step-D call; the host copies stay
+  // here while their uploads may be in flight
+  bool stepd_ready = false;
+  std::vector<int32_t> csr_rp, csr_ent;
+  std::vector<double> csr_wd, inv_d;
+  std::vector<float> csr_wf, inv_f;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int g_algo = -1;
