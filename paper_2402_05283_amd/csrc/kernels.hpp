@@ -48,12 +48,12 @@ template <> struct ColCfg<1024> { static constexpr int R1 = 32, R2 = 32, C = 8, 
 // row group, reached with DPP lane moves.
 template <int N> struct RowCfg;
 template <> struct RowCfg<64> { static constexpr int F1 = 4, F2 = 8, RPB = 32; };
-template <> struct RowCfg<128> { static constexpr int F1 = 8, F2 = 8, RPB = 16; };
-template <> struct RowCfg<256> { static constexpr int F1 = 8, F2 = 16, RPB = 16; };
+template <> struct RowCfg<128> { static constexpr int F1 = 8, F2 = 8, RPB = 8; };
+template <> struct RowCfg<256> { static constexpr int F1 = 8, F2 = 16, RPB = 8; };
 template <> struct RowCfg<192> { static constexpr int F1 = 4, F2 = 24, RPB = 32; };
-template <> struct RowCfg<384> { static constexpr int F1 = 8, F2 = 24, RPB = 16; };
-template <> struct RowCfg<512> { static constexpr int F1 = 16, F2 = 16, RPB = 16; };
-template <> struct RowCfg<1024> { static constexpr int F1 = 16, F2 = 32, RPB = 16; };
+template <> struct RowCfg<384> { static constexpr int F1 = 8, F2 = 24, RPB = 8; };
+template <> struct RowCfg<512> { static constexpr int F1 = 16, F2 = 16, RPB = 8; };
+template <> struct RowCfg<1024> { static constexpr int F1 = 16, F2 = 32, RPB = 8; };
 
 template <int N> struct RowGeom {
   static constexpr int L = N / 2;
