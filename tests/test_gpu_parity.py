@@ -581,3 +581,9 @@ def test_api_errors(torch):
     assert e.value.status == -4                    # not at an episode end
     plan.iterate(2)
     plan.assemble_volume()
+    with pytest.raises(cp.CpraError) as e:
+        plan.set_chunk(-1)
+    assert e.value.status == -1                    # negative chunk size
+    k = plan.k
+    plan.iterate(0)                                # an empty request is a no-op
+    assert plan.k == k
