@@ -40,7 +40,8 @@ N, NP, ITERS, N_EI, BETA = 512, 360, 200, 10, 0.9
 
 
 def algorithmic_bytes(N, Np, n_ei, amp_bytes=8, real_bytes=4):
-    """Bytes each pass must move per launch, averaged over an episode.
+    """Bytes each pass must move per launch, averaged over an episode (the boundary launch's
+    extra neighbour reads spread over the n_ei launches of the episode).
 
     Column pass per angle: read P and write Pmid (N x N/2 complex each) and
     read the amplitude pairs (N x N/2 pairs); at an episode boundary it also
