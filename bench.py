@@ -562,8 +562,8 @@ def main():
         print(summarize_pmc(*args.summarize_pmc, cmd), end="")
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU (multi-GPU sharding is a design note only); "
-              "use --gpus 1", file=sys.stderr)
+        print("bench.py: the library runs on exactly one GPU (sharding across GPUs is described, not "
+              "implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
