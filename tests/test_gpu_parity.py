@@ -1,9 +1,13 @@
 """GPU path vs the FP64 oracle, through the C ABI (needs an MI355X).
 
 Tolerances (relative L2 over the whole scan, oracle as reference):
-  FP32 plans: 1e-6 on the initial objects, 1e-5 after one iteration, 1e-3 on
-  the final object after 200 iterations of the 64x64x16 scan;
-  FP64 plans: 1e-12 / 1e-12 / 1e-9.
+  FP32 plans: 1e-6 on the initial objects, 1e-5 for one iteration (from W_0, or
+  from the oracle's own state at any step of the 200-iteration schedule), 1e-4
+  on whole ER runs; FP64 plans: 1e-12 / 1e-12 / 1e-9, and 1e-6 on 30 whole HIO
+  iterations.  Whole 200-iteration HIO runs are compared by their final error
+  level only: HIO amplifies a 1e-15 perturbation of the start to ~7e-2 by
+  iteration 200 (tests/test_oracle_sensitivity.py), so no two implementations
+  agree pointwise there.
 A pixel whose HIO sign decision g' >= 0 sits within rounding of zero may
 legitimately take either branch; one-iteration checks exclude such pixels
 from the norm and require their value to be one of the two branches.
