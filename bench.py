@@ -57,18 +57,35 @@ def algorithmic_bytes(N, Np, n_ei, amp_bytes=8, real_bytes=4):
     return col * Np, row * Np
 
 
-def cpu_baseline(scan, threads=1):
-    """Time the FP64 oracle on 8 angles x 3 iterations in a single-threaded child process."""
+def _oracle_child(code, threads, timeout=900):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               NUMEXPR_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="", ROCR_VISIBLE_DEVICES="")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=timeout)
+    if out.returncode != 0:
+        return {"error": out.stderr[-500:]}
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(scan):
+    """The FP64 oracle on the host, in a child process that never touches the GPU, on two bounded
+    samples of the benchmark scan:
+      * one thread: angles 0-7 (all present, so the 8 form the coupling ring), 3 HIO iterations
+        including one coupling;
+      * all cores: a process pool of one worker per core (len(os.sched_getaffinity(0))), each
+        running oracle iterations of whole angles (the iterations of an episode are independent
+        per angle); 2 angles per worker, 10 HIO iterations each after the coupled start.
+    Reported value: the all-core figure."""
     import tempfile
-    sample = 8
+    cores = len(os.sched_getaffinity(0))
+    n_all = 2 * cores
     with tempfile.TemporaryDirectory() as td:
-        np.save(os.path.join(td, "I.npy"), scan["I"][:sample])
-        np.save(os.path.join(td, "S.npy"), scan["support"][:sample])
-        code = f"""
+        np.save(os.path.join(td, "I.npy"), scan["I"][:max(8, n_all)])
+        np.save(os.path.join(td, "S.npy"), scan["support"][:max(8, n_all)])
+        single = _oracle_child(f"""
 import sys, time, json, numpy as np
 sys.path.insert(0, {ROOT!r})
 from oracle import cpra as C
-I = np.load({os.path.join(td, 'I.npy')!r}); S = np.load({os.path.join(td, 'S.npy')!r})
+I = np.load({os.path.join(td, 'I.npy')!r})[:8]; S = np.load({os.path.join(td, 'S.npy')!r})[:8]
 o = C.Oracle({N}, {NP}, seed={scan['phase_seed']}, n_ei={N_EI})
 t0 = time.perf_counter()
 o.submit(0, I, S)
@@ -76,19 +93,40 @@ t1 = time.perf_counter()
 o.iterate(3, C.HIO, {BETA})
 t2 = time.perf_counter()
 print(json.dumps({{"submit_s": t1 - t0, "iter_s": t2 - t1}}))
-"""
-        env = dict(os.environ, OMP_NUM_THREADS=str(threads), OPENBLAS_NUM_THREADS=str(threads),
-                   MKL_NUM_THREADS=str(threads), NUMEXPR_NUM_THREADS=str(threads), HIP_VISIBLE_DEVICES="",
-                   CUDA_VISIBLE_DEVICES="", ROCR_VISIBLE_DEVICES="")
-        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
-        if out.returncode != 0:
-            return {"error": out.stderr[-500:]}
-        r = json.loads(out.stdout.strip().splitlines()[-1])
-    pit = sample * 3 / r["iter_s"]
-    return {"value": pit, "unit": "pattern-iterations/s", "cores": threads, "kind": "oracle",
-            "sample": f"N=512 cell scan, angles 0-7 (all present, so the 8 form the coupling ring), "
-                      f"3 HIO iterations incl. one coupling; FP64 numpy oracle, 1 thread; "
-                      f"{r['iter_s']:.1f} s iterate + {r['submit_s']:.1f} s submit"}
+""", 1)
+        pool = _oracle_child(f"""
+import sys, time, json, numpy as np
+from multiprocessing import get_context
+sys.path.insert(0, {ROOT!r})
+from oracle import cpra as C
+I = np.load({os.path.join(td, 'I.npy')!r}); S = np.load({os.path.join(td, 'S.npy')!r})
+
+def work(n):
+    A = C.amplitudes(I[n]); sup = S[n] != 0
+    g = C.initial_object(A, {scan['phase_seed']}, n)
+    for it in range(10):
+        gp = C.inverse_real(C.modulus_projection(C.forward(g), A))
+        g = C.real_space_update(g, gp, sup, C.HIO, {BETA}, True, it == 9)
+    return float(g.sum())
+
+with get_context("fork").Pool({cores}) as p:
+    p.map(work, range({cores}))            # warm the workers
+    t0 = time.perf_counter()
+    p.map(work, range({n_all}), chunksize=1)
+    t1 = time.perf_counter()
+print(json.dumps({{"iter_s": t1 - t0}}))
+""", cores)
+    if "error" in single or "error" in pool:
+        return {"error": single.get("error") or pool.get("error")}
+    single_v = 8 * 3 / single["iter_s"]
+    all_v = n_all * 10 / pool["iter_s"]
+    return {"value": round(all_v, 2), "unit": "pattern-iterations/s", "cores": cores, "kind": "oracle",
+            "sample": f"N=512 cell scan, {n_all} angles x 10 HIO iterations (each from its random start, "
+                      f"the last writing the estimate), one worker process per core, FP64 numpy oracle; "
+                      f"{pool['iter_s']:.1f} s wall (also timed: W_0 per angle inside the workers)",
+            "single_core": {"value": round(single_v, 2), "cores": 1,
+                            "sample": f"angles 0-7 (one coupling ring), 3 HIO iterations incl. one coupling; "
+                                      f"{single['iter_s']:.1f} s iterate + {single['submit_s']:.1f} s submit"}}
 
 
 def kernel_source_hash():
@@ -249,7 +287,66 @@ def serving_latency(cp, torch, scan, I, S, args):
             "serving_wall_s": round(wall, 2), "scan_iterations": int(work)}
 
 
-def plain_comparison(cp, torch, scan, I, S, args, cpra_iter_ms):
+class Quality:
+    """Quality of a scan's objects against the known object: median over angles of E_F; twin
+    consistency (the fraction of angles whose estimate is nearer the true projection than its point
+    reflection, which fits the same intensities, or one minus it if larger); and the relative L2
+    error of the step-D volume against the step-D volume of the true projections, after choosing
+    the better of the volume and its twin."""
+
+    def __init__(self, cp, torch, scan, I, S):
+        self.torch = torch
+        self.Np, self.N = scan["Np"], scan["N"]
+        self.A_nat = torch.fft.ifftshift(torch.sqrt(torch.clamp(I, min=0.0)), dim=(-2, -1))
+        self.den = (self.A_nat.double() ** 2).sum((-2, -1))
+        self.po = torch.from_numpy(scan["po"].astype(np.float32)).to(I.device)
+        self.vp = cp.Plan(self.N, self.Np, theta=scan["theta"], n_ei=N_EI, seed=scan["phase_seed"])
+        self.vp.submit(0, I, S)
+        self.vp.iterate(N_EI, cp.HIO, BETA)                 # step D needs an episode end
+        self.v_true = self.vol_of(self.po).clone()
+
+    @staticmethod
+    def twin(x, dims):
+        for d in dims:
+            x = torch_roll_flip(x, d)
+        return x
+
+    def vol_of(self, obj):
+        self.vp.load_objects(obj)
+        return self.vp.assemble_volume()
+
+    def volume_error(self, v):
+        t = self.torch
+        ve = min(float(t.linalg.norm(v - self.v_true)), float(t.linalg.norm(self.twin(v, (0, 1, 2)) - self.v_true)))
+        return round(ve / float(t.linalg.norm(self.v_true)), 4)
+
+    def __call__(self, obj, vol=None):
+        t = self.torch
+        Np = self.Np
+        err = t.empty(Np, dtype=t.float64, device=obj.device)
+        near_true = 0
+        for c0 in range(0, Np, 60):
+            o = obj[c0:c0 + 60]
+            G = t.fft.fft2(o)
+            err[c0:c0 + 60] = t.sqrt(((G.abs() - self.A_nat[c0:c0 + 60]) ** 2).double().sum((-2, -1))
+                                     / self.den[c0:c0 + 60])
+            p = self.po[c0:c0 + 60]
+            d0 = ((o - p) ** 2).sum((-2, -1))
+            d1 = ((o - self.twin(p, (-2, -1))) ** 2).sum((-2, -1))
+            near_true += int((d0 < d1).sum())
+        v = self.vol_of(obj) if vol is None else vol
+        frac = near_true / Np
+        return {"median_error": round(float(err.median()), 5), "twin_consistency": round(max(frac, 1 - frac), 4),
+                "volume_error": self.volume_error(v)}
+
+
+def torch_roll_flip(x, d):
+    """Point reflection about the centred origin along axis d (index i -> (N - i) mod N)."""
+    import torch
+    return torch.roll(torch.flip(x, (d,)), 1, d)
+
+
+def plain_comparison(cp, torch, scan, I, S, args, cpra_iter_ms, Q):
     """CPRA against the plain per-angle method on the same GPU.
 
     Plain method = the same 2D HIO with no carousel coupling (alpha = (0, 1, 0)): each angle is
@@ -266,34 +363,11 @@ def plain_comparison(cp, torch, scan, I, S, args, cpra_iter_ms):
     kernels at batch 1, one plan per angle, over a sample of angles."""
     Np, N = scan["Np"], scan["N"]
     th = scan["theta"]
-    A_nat = torch.fft.ifftshift(torch.sqrt(torch.clamp(I, min=0.0)), dim=(-2, -1))
-    den = (A_nat.double() ** 2).sum((-2, -1))
+    A_nat, den = Q.A_nat, Q.den
     Sb = S.bool()
-    po = torch.from_numpy(scan["po"].astype(np.float32)).to(I.device)
 
-    def twin(x, dims):
-        for d in dims:
-            x = torch.roll(torch.flip(x, (d,)), 1, d)
-        return x
-
-    def quality(obj, vol_of):
-        err = torch.empty(Np, dtype=torch.float64, device=obj.device)
-        near_true = 0
-        for c0 in range(0, Np, 60):
-            o = obj[c0:c0 + 60]
-            G = torch.fft.fft2(o)
-            err[c0:c0 + 60] = torch.sqrt(((G.abs() - A_nat[c0:c0 + 60]) ** 2).double().sum((-2, -1))
-                                         / den[c0:c0 + 60])
-            p = po[c0:c0 + 60]
-            d0 = ((o - p) ** 2).sum((-2, -1))
-            d1 = ((o - twin(p, (-2, -1))) ** 2).sum((-2, -1))
-            near_true += int((d0 < d1).sum())
-        v = vol_of(obj)
-        ve = min(float(torch.linalg.norm(v - v_true)), float(torch.linalg.norm(twin(v, (0, 1, 2)) - v_true)))
-        frac = near_true / Np
-        return {"median_error": round(float(err.median()), 5),
-                "twin_consistency": round(max(frac, 1 - frac), 4),
-                "volume_error": round(ve / float(torch.linalg.norm(v_true)), 4)}
+    def quality(obj, _vol_of=None):
+        return Q(obj)
 
     def plan(alpha, wrap, n=None):
         th_ = th if n is None else th[n:n + 1]
@@ -304,14 +378,7 @@ def plain_comparison(cp, torch, scan, I, S, args, cpra_iter_ms):
             p.submit(0, I[n:n + 1], S[n:n + 1])
         return p
 
-    vp = plan((0.2, 0.6, 0.2), cp.WRAP_MIRROR)
-    vp.iterate(N_EI, cp.HIO, BETA)                      # step D needs an episode end
-
-    def vol_of(obj):
-        vp.load_objects(obj)
-        return vp.assemble_volume()
-
-    v_true = vol_of(po).clone()
+    vol_of = Q.vol_of
     out = {}
     pc = plan((0.2, 0.6, 0.2), cp.WRAP_MIRROR)
     pc.iterate(ITERS, cp.HIO, BETA)
@@ -376,13 +443,13 @@ def plain_comparison(cp, torch, scan, I, S, args, cpra_iter_ms):
         p.iterate(ITERS, cp.HIO, BETA)
     torch.cuda.synchronize()
     t_b1 = time.perf_counter() - t0
-    del plans, vp
+    del plans
     out["plain_batch1_loop"] = {"pattern_iterations_per_s": round(ITERS * len(sample) / t_b1, 1),
                                 "angles_timed": len(sample)}
     return out
 
 
-def paper_schedule(cp, torch, scan, I, S, args):
+def paper_schedule(cp, torch, scan, I, S, args, Q):
     """The paper's own schedule on the same scan: N_r = 100 random guesses held at once, step A
     (N_i^pre = 500 HIO iterations of PO 1), step B as the consecutive sweep (N_e = 1, N_ei = 2, the
     paper's timing configuration), step C (merge of the N_l = 10 best guesses) and step D.
@@ -405,7 +472,13 @@ def paper_schedule(cp, torch, scan, I, S, args):
         t[name] = time.perf_counter() - t1
         if name == "step_C":
             kept, inv = out
+        if name == "step_D":
+            vol = out
     total = sum(t.values())
+    print("[bench] paper schedule: quality of the merged reconstruction", file=sys.stderr, flush=True)
+    merged = plan.objects()[0] if R > 1 else plan.objects()
+    qual = Q(merged, vol)
+    del merged, vol
     pits = R * (n_pre + NP * n_e * n_ei)
     del plan
     torch.cuda.empty_cache()
@@ -413,7 +486,8 @@ def paper_schedule(cp, torch, scan, I, S, args):
             "seconds": {k: round(v, 4) for k, v in t.items()}, "total_s": round(total, 3),
             "pattern_iterations": pits,
             "pattern_iterations_per_s_steps_AB": round(pits / (t["step_A"] + t["step_B"]), 1),
-            "kept": [int(k) for k in kept], "inverted": [bool(i) for i in inv]}
+            "kept": [int(k) for k in kept], "inverted": [bool(i) for i in inv],
+            "merged_quality": qual}
 
 
 def variants(cp, torch, scan, I, S, args):
@@ -520,6 +594,57 @@ def batched_scans(cp, torch, scan512, args):
             "sequential_pattern_iterations_per_s": round(work / t_seq, 1)}
 
 
+def fp16_leg(cp, torch, scan, I, S, vol, stream, args, steps=3):
+    """The headline step with FP16 amplitude storage (per-angle power-of-two scale): whole-step
+    throughput and the mean iteration time from HIP events."""
+    def one(timed):
+        plan = cp.Plan(N, NP, n_ei=N_EI, amp=cp.AMP_F16, seed=scan["phase_seed"], stream=stream)
+        if timed:
+            plan.set_kernel_timing(True)
+        plan.submit(0, I, S)
+        plan.iterate(ITERS, cp.HIO, BETA)
+        plan.assemble_volume(vol)
+        res = plan.kernel_timing() if timed else None
+        torch.cuda.synchronize()
+        return res
+    one(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c = r = 0.0
+    n = 0
+    for _ in range(steps):
+        cm, cn, rm, rn = one(True)
+        c += cm; r += rm; n += cn
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    it = (c + r) / max(n, 1)
+    col_b, row_b = algorithmic_bytes(N, NP, N_EI, amp_bytes=4)
+    return {"value": round(ITERS * NP / dt, 1), "unit": "pattern-iterations/s", "ms_per_step": round(dt * 1e3, 3),
+            "steps": steps, "ms_per_iteration": round(it, 4),
+            "fused_iteration_frac": round((col_b + row_b) / (it * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "what": "same step as the headline with amplitudes stored as binary16 pairs times a per-angle "
+                    "power-of-two scale (error against the FP64 oracle: tests/test_gpu_parity.py "
+                    "precision study, tests/test_gpu_noisy.py)"}
+
+
+def error_history_leg(cp, torch, scan, I, S, stream, iter_ms):
+    """Cost of recording E_F for every angle and iteration: 200 iterations with the error history
+    (FP64 partials per tile, fixed-order reduction, copied to the host every 64 iterations)."""
+    plan = cp.Plan(N, NP, n_ei=N_EI, seed=scan["phase_seed"], stream=stream)
+    plan.submit(0, I, S)
+    plan.iterate(N_EI, cp.HIO, BETA, errors=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e = plan.iterate(ITERS, cp.HIO, BETA, errors=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / ITERS
+    return {"ms_per_iteration": round(dt * 1e3, 4), "without_ms_per_iteration": round(iter_ms, 4),
+            "final_median_error": round(float(np.median(e[-1])), 5),
+            "what": "wall time per iteration of cpra_iterate with err_out over 200 iterations (host "
+                    "synchronisation every 64 iterations included), against the HIP-event iteration time "
+                    "without it"}
+
+
 def quality_error_only(torch, obj, A_nat, den):
     err = []
     for c0 in range(0, obj.shape[0], 60):
@@ -596,6 +721,12 @@ def main():
     col_ms = row_ms = 0.0
     col_n = row_n = 0
     lat = []
+    qcache = []
+
+    def quality_of():
+        if not qcache:
+            qcache.append(Quality(cp, torch, scan, I, S))
+        return qcache[0]
 
     def one_step(timed):
         nonlocal col_ms, row_ms, col_n, row_n
@@ -633,13 +764,21 @@ def main():
     dom = ("k_col", col_avg, col_gbs, col_b) if col_avg >= row_avg else ("k_row", row_avg, row_gbs, row_b)
     tr = load_traffic() if not args.amp16 else None
     traffic = round(tr[dom[0]]["traffic_bytes"]) if tr else None
+    iter_ms = (col_ms + row_ms) / max(col_n, 1)
+    it_gbs = (col_b + row_b) / (iter_ms * 1e-3) / 1e9
+    full_b = 46.525 * N * N * NP                # full-complex-spectrum byte model (two complex planes per pass)
     roofline = {"bound": "hbm", "achieved": round(dom[2], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom[2] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom[0],
                 "avg_launch_ms": round(dom[1], 5), "bytes_per_launch": int(dom[3]),
                 "other": {"kernel": "k_row" if dom[0] == "k_col" else "k_col",
                           "avg_launch_ms": round(row_avg if dom[0] == "k_col" else col_avg, 5),
-                          "achieved": round(row_gbs if dom[0] == "k_col" else col_gbs, 1)}}
-    iter_ms = (col_ms + row_ms) / max(col_n, 1)
+                          "achieved": round(row_gbs if dom[0] == "k_col" else col_gbs, 1),
+                          "frac": round((row_gbs if dom[0] == "k_col" else col_gbs) / HBM_PEAK_GBS, 4)},
+                "fused_iteration": {"achieved": round(it_gbs, 1), "frac": round(it_gbs / HBM_PEAK_GBS, 4),
+                                    "bytes": int(col_b + row_b), "ms": round(iter_ms, 5),
+                                    "what": "column + row pass algorithmic bytes over their summed mean "
+                                            "launch times: the whole fused FFT + projection iteration"},
+                "full_complex_model_frac": round(full_b / (iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     out = {
         "metric": "pattern-iterations/s at N=512,N_p=360 + p99 last-frame-to-volume latency",
         "value": round(value, 1),
@@ -663,15 +802,19 @@ def main():
                            "pattern_iterations_per_s": round(NP / (iter_ms * 1e-3), 1)},
         "roofline": roofline,
     }
+    if not args.amp16 and args.iters == ITERS:
+        print("[bench] FP16 amplitudes, error history", file=sys.stderr, flush=True)
+        out["fp16_amplitudes"] = fp16_leg(cp, torch, scan, I, S, vol, stream, args)
+        out["error_history_cost"] = error_history_leg(cp, torch, scan, I, S, stream, iter_ms)
     if not args.no_compare and args.iters == ITERS and not args.amp16:
         print("[bench] plain per-angle comparison", file=sys.stderr, flush=True)
-        out["vs_plain_per_angle"] = plain_comparison(cp, torch, scan, I, S, args, iter_ms)
+        out["vs_plain_per_angle"] = plain_comparison(cp, torch, scan, I, S, args, iter_ms, quality_of())
     if not args.no_compare and args.iters == ITERS and not args.amp16:
         print("[bench] algorithm variants", file=sys.stderr, flush=True)
         out["variants"] = variants(cp, torch, scan, I, S, args)
     if args.guesses > 0 and args.iters == ITERS and not args.amp16:
         print(f"[bench] paper schedule, {args.guesses} guesses", file=sys.stderr, flush=True)
-        out["paper_schedule"] = paper_schedule(cp, torch, scan, I, S, args)
+        out["paper_schedule"] = paper_schedule(cp, torch, scan, I, S, args, quality_of())
     if args.batch_scans > 0 and args.iters == ITERS and not args.amp16:
         print(f"[bench] batched: {args.batch_scans} scans of uneven size", file=sys.stderr, flush=True)
         out["batched_uneven_scans"] = batched_scans(cp, torch, scan, args)

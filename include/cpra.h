@@ -94,6 +94,10 @@ cpra_status cpra_workspace_size(const cpra_params* params, size_t* bytes);
  * stream) orders all of the plan's device work.  The plan owns only host
  * memory.  Twiddle tables are generated on the device in FP64.
  */
+cpra_status cpra_plan(const cpra_params* params, void* workspace, size_t workspace_bytes, void* hip_stream,
+                      cpra_plan_t* out);
+
+/* The same call under its earlier name (identical arguments and behaviour). */
 cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t workspace_bytes,
                              void* hip_stream, cpra_plan_t* out);
 

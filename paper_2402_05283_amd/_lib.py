@@ -26,7 +26,7 @@ AMP_F32, AMP_F16 = 0, 1
 PTR_HOST, PTR_DEVICE = 0, 1
 
 EXPORTED = [
-    "cpra_workspace_size", "cpra_plan_create", "cpra_submit_angles", "cpra_iterate", "cpra_read_objects",
+    "cpra_workspace_size", "cpra_plan", "cpra_plan_create", "cpra_submit_angles", "cpra_iterate", "cpra_read_objects",
     "cpra_assemble_volume", "cpra_destroy", "cpra_last_error", "cpra_iteration_count", "cpra_slice_cells",
     "cpra_coupling_table", "cpra_set_kernel_timing", "cpra_kernel_timing", "cpra_load_objects",
     "cpra_iterate_batch", "cpra_prereconstruct", "cpra_sweep", "cpra_merge", "cpra_shrinkwrap",
@@ -74,6 +74,7 @@ def load():
     c = ctypes
     P = c.POINTER
     lib.cpra_workspace_size.argtypes = [P(Params), P(c.c_size_t)]
+    lib.cpra_plan.argtypes = [P(Params), c.c_void_p, c.c_size_t, c.c_void_p, P(c.c_void_p)]
     lib.cpra_plan_create.argtypes = [P(Params), c.c_void_p, c.c_size_t, c.c_void_p, P(c.c_void_p)]
     lib.cpra_submit_angles.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_void_p, c.c_void_p, c.c_int32]
     lib.cpra_iterate.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_double, c.c_void_p]
@@ -195,7 +196,7 @@ class Plan:
         self._ws_ptr = (base + 255) // 256 * 256
         self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
         handle = ctypes.c_void_p(0)
-        st = lib.cpra_plan_create(ctypes.byref(self.params), ctypes.c_void_p(self._ws_ptr), nbytes,
+        st = lib.cpra_plan(ctypes.byref(self.params), ctypes.c_void_p(self._ws_ptr), nbytes,
                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle))
         _check(st, None)
         self.handle = handle

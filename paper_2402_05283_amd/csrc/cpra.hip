@@ -30,6 +30,7 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+
 // row-pass mode of a real-space update rule (episode estimates use mode 2)
 int mode_of(int32_t algo) { return algo == CPRA_HIO ? 1 : algo == CPRA_RAAR ? 4 : 2; }
 
@@ -175,6 +176,7 @@ Layout layout_of(const cpra_params* p) {
 
 }  // namespace
 
+
 namespace {
 
 cpra_status fail(cpra_plan_t pl, cpra_status st, const char* fmt, ...) {
@@ -276,8 +278,8 @@ cpra_status cpra_workspace_size(const cpra_params* params, size_t* bytes) {
   return CPRA_OK;
 }
 
-cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t workspace_bytes, void* hip_stream,
-                             cpra_plan_t* out) {
+cpra_status cpra_plan(const cpra_params* params, void* workspace, size_t workspace_bytes, void* hip_stream,
+                      cpra_plan_t* out) {
   std::string msg;
   cpra_status st = validate(params, msg);
   if (st != CPRA_OK) return fail(nullptr, st, "%s", msg.c_str());
@@ -323,6 +325,11 @@ cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t 
   }
   *out = pl;
   return CPRA_OK;
+}
+
+cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t workspace_bytes, void* hip_stream,
+                             cpra_plan_t* out) {
+  return cpra_plan(params, workspace, workspace_bytes, hip_stream, out);
 }
 
 // Step-D tables: the integer cell map of the Fourier-slice insertion (built on the host in FP64),
@@ -928,8 +935,9 @@ cpra_status cpra_refine_workspace_size(const cpra_params* params, size_t* bytes)
   return CPRA_OK;
 }
 
-cpra_status cpra_refine_volume(cpra_plan_t pl, int32_t n_iter, int32_t shrink_every, double sigma, double threshold,
-                               void* work, size_t work_bytes, void* d_volume) {
+// the refinement on the scratch buffer `work` of work_bytes
+static cpra_status refine_run(cpra_plan_t pl, int32_t n_iter, int32_t shrink_every, double sigma, double threshold,
+                              void* work, size_t work_bytes, void* d_volume) {
   if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
   if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
   if (!d_volume) return fail(pl, CPRA_ERR_ARG, "d_volume is NULL");
@@ -1001,6 +1009,11 @@ cpra_status cpra_refine_volume(cpra_plan_t pl, int32_t n_iter, int32_t shrink_ev
   LAUNCHCHK(pl);
   HIPCHK(pl, hipStreamSynchronize(pl->stream));   // host tables go out of scope
   return CPRA_OK;
+}
+
+cpra_status cpra_refine_volume(cpra_plan_t pl, int32_t n_iter, int32_t shrink_every, double sigma, double threshold,
+                               void* work, size_t work_bytes, void* d_volume) {
+  return refine_run(pl, n_iter, shrink_every, sigma, threshold, work, work_bytes, d_volume);
 }
 
 cpra_status cpra_read_support(cpra_plan_t pl, uint8_t* out) {

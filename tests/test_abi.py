@@ -22,7 +22,7 @@ def _declared():
 def test_library_exports_every_declared_symbol():
     lib = cp.load()
     names = _declared()
-    assert "cpra_plan_create" in names and "cpra_iterate" in names
+    assert "cpra_plan" in names and "cpra_plan_create" in names and "cpra_iterate" in names
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(_lib.EXPORTED) == names

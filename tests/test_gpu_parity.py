@@ -1,6 +1,7 @@
 """GPU path vs the FP64 oracle, through the C ABI (needs an MI355X).
 
-Tolerances (relative L2 over the whole scan, oracle as reference):
+Tolerances (relative L2 over the whole scan, oracle as reference; every single angle must also be
+within the tolerance for one-iteration checks and within twice it for whole runs):
   FP32 plans: 1e-6 on the initial objects, 1e-5 for one iteration (from W_0, or
   from the oracle's own state at any step of the 200-iteration schedule), 1e-4
   on whole ER runs; FP64 plans: 1e-12 / 1e-12 / 1e-9, and 1e-6 on 30 whole HIO
@@ -15,7 +16,7 @@ from the norm and require their value to be one of the two branches.
 import numpy as np
 import pytest
 
-from gpu_util import banner, last_step_parity, rel_l2, require_gpu, run_gpu, run_oracle
+from gpu_util import banner, last_step_parity, rel_l2, require_gpu, run_gpu, run_oracle, scan_rel
 from synth import make_scan
 
 pytestmark = pytest.mark.gpu
@@ -37,7 +38,7 @@ def test_initial_objects(torch, N, real):
     _, obj, _ = run_gpu(scan, [], real=real)
     o, _ = run_oracle(scan, [])
     tol = 1e-6 if real == F32 else 1e-12
-    assert rel_l2(obj, o.g) <= tol
+    assert scan_rel(obj, o.g) <= tol
 
 
 @pytest.mark.parametrize("real", [F32, F64])
@@ -104,7 +105,7 @@ def test_c1_short_run_fp64(torch):
     banner("c1 30 iterations fp64")
     _, obj, errs = run_gpu(scan, sched, real=F64)
     o, oerrs = run_oracle(scan, sched)
-    assert rel_l2(obj, o.g) <= 1e-6        # the oracle against itself perturbed by 1e-15 drifts to 3e-9
+    assert scan_rel(obj, o.g) <= 1e-6        # the oracle against itself perturbed by 1e-15 drifts to 3e-9
     assert rel_l2(errs[0], oerrs[0]) <= 1e-6
 
 
@@ -118,7 +119,7 @@ def test_c1_er_run(torch, real):
     _, obj, errs = run_gpu(scan, sched, real=real)
     o, oerrs = run_oracle(scan, sched)
     tol = 1e-4 if real == F32 else 1e-9
-    assert rel_l2(obj, o.g) <= tol
+    assert scan_rel(obj, o.g) <= tol
     assert rel_l2(errs[0], oerrs[0]) <= tol
 
 
@@ -150,7 +151,7 @@ def test_er_plain_wrap_unmeasured_no_positivity(torch, real):
     _, obj, errs = run_gpu(scan, sched, real=real, **kw)
     o, oerrs = run_oracle(scan, sched, **kw)
     tol = 1e-4 if real == F32 else 1e-10
-    assert rel_l2(obj, o.g) <= tol
+    assert scan_rel(obj, o.g) <= tol
     for a, b in zip(errs, oerrs):
         assert rel_l2(a, b) <= tol
 
@@ -163,7 +164,7 @@ def test_few_angles(torch, Np):
     for wrap in (0, 1):
         _, obj, _ = run_gpu(scan, sched, real=F64, n_ei=4, wrap=wrap)
         o, _ = run_oracle(scan, sched, n_ei=4, wrap=wrap)
-        assert rel_l2(obj, o.g) <= 1e-10
+        assert scan_rel(obj, o.g) <= 1e-10
 
 
 def test_partial_angle_sets(torch):
@@ -188,7 +189,7 @@ def test_partial_angle_sets(torch):
         assert np.array_equal(np.isnan(e), np.isnan(oe))
         assert rel_l2(np.nan_to_num(e), np.nan_to_num(oe)) <= 1e-10
     obj = plan.objects().cpu().numpy()
-    assert rel_l2(obj, o.g) <= 1e-10
+    assert scan_rel(obj, o.g) <= 1e-10
 
 
 @pytest.mark.parametrize("real", [F32, F64])
@@ -375,7 +376,7 @@ def test_raar_run_fp64(torch):
     banner("raar 30 iterations fp64")
     _, obj, errs = run_gpu(scan, [(30, cp.RAAR, 0.9)], real=F64)
     o, oerrs = run_oracle(scan, [(30, C.RAAR, 0.9)])
-    assert rel_l2(obj, o.g) <= 1e-6
+    assert scan_rel(obj, o.g) <= 1e-6
     assert rel_l2(errs[0], oerrs[0]) <= 1e-6
 
 
@@ -398,7 +399,7 @@ def test_k_tap_coupling(torch, real):
     o.submit(0, scan["I"], scan["support"])
     oe = o.iterate(12, algo, beta)
     torch.cuda.synchronize()
-    assert rel_l2(plan.objects().cpu().numpy(), o.g) <= tol
+    assert scan_rel(plan.objects().cpu().numpy(), o.g) <= tol
     assert rel_l2(e, oe) <= tol
     # partial set: angles 0-2 and 5 present
     plan = cp.Plan(64, 8, theta=scan["theta"], n_ei=5, real=real, seed=scan["phase_seed"], taps=taps)
@@ -411,7 +412,7 @@ def test_k_tap_coupling(torch, real):
     torch.cuda.synchronize()
     got = plan.objects().cpu().numpy()
     pres = [0, 1, 2, 5]
-    assert rel_l2(got[pres], o.g[pres]) <= tol
+    assert scan_rel(got[pres], o.g[pres]) <= tol
     # consecutive sweep with five taps, two guesses
     plan = cp.Plan(64, 8, theta=scan["theta"], n_ei=3, real=real, seed=scan["phase_seed"], taps=taps, n_guess=2)
     plan.submit(0, scan["I"], scan["support"])
@@ -420,7 +421,45 @@ def test_k_tap_coupling(torch, real):
     plan.sweep(1, algo, beta)
     gs.sweep(1, algo, beta)
     torch.cuda.synchronize()
-    assert rel_l2(plan.objects().cpu().numpy(), gs.g) <= tol
+    assert scan_rel(plan.objects().cpu().numpy(), gs.g) <= tol
+
+
+@pytest.mark.parametrize("real", [F64, F32])
+def test_k_tap_coupling_n512(torch, real):
+    """Eq. 4 with five taps at N = 512, the size the benchmark times it at (the 16-column
+    half-chunk plane layout and the paired column pass): a Jacobi run through two coupling passes
+    over six angles (every tap crosses the seam for some angle), then the consecutive sweep with two
+    guesses.  FP64 with HIO (1e-10); FP32 with ER (1e-4)."""
+    import paper_2402_05283_amd as cp
+    from oracle import cpra as C
+    from oracle import schedule as SC
+    taps = (0.05, 0.15, 0.6, 0.15, 0.05)
+    N, Np = 512, 6
+    scan = make_scan(1, N=N, Np=Np)
+    algo, beta, tol = (HIO, 0.9, 1e-10) if real == F64 else (ER, 0.0, 1e-4)
+    banner(f"k-tap coupling N=512 real={real}")
+    plan = cp.Plan(N, Np, theta=scan["theta"], n_ei=4, real=real, seed=scan["phase_seed"], taps=taps)
+    plan.submit(0, torch.from_numpy(scan["I"]).cuda(), torch.from_numpy(scan["support"]).cuda())
+    e = plan.iterate(9, algo, beta, errors=True)
+    o = C.Oracle(N, Np, theta=scan["theta"], n_ei=4, seed=scan["phase_seed"], taps=taps)
+    o.submit(0, scan["I"], scan["support"])
+    oe = o.iterate(9, algo, beta)
+    torch.cuda.synchronize()
+    r = scan_rel(plan.objects().cpu().numpy(), o.g)
+    print(f"k-tap jacobi N=512 real={real}: {r:.2e}")
+    assert r <= tol
+    assert rel_l2(e, oe) <= tol
+    banner(f"k-tap sweep N=512 real={real}")
+    plan = cp.Plan(N, Np, theta=scan["theta"], n_ei=2, real=real, seed=scan["phase_seed"], taps=taps, n_guess=2)
+    plan.submit(0, torch.from_numpy(scan["I"]).cuda(), torch.from_numpy(scan["support"]).cuda())
+    gs = SC.GuessSet(N, Np, 2, theta=scan["theta"], n_ei=2, seed=scan["phase_seed"], taps=taps)
+    gs.submit(scan["I"], scan["support"])
+    plan.sweep(1, algo, beta)
+    gs.sweep(1, algo, beta)
+    torch.cuda.synchronize()
+    r = scan_rel(plan.objects().cpu().numpy(), gs.g)
+    print(f"k-tap sweep N=512 real={real}: {r:.2e}")
+    assert r <= tol
 
 
 def test_precision_study_n512(torch):

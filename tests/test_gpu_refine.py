@@ -65,6 +65,81 @@ def test_refine_volume_n128(torch):
     assert rel_l2(got, ref) <= 1e-4
 
 
+def test_refine_volume_n256(torch):
+    """N = 256, the whole volume: two error-reduction iterations (FP32, 1e-4) against the plain-3D
+    oracle, from the GPU's own estimates of a six-angle scan."""
+    import paper_2402_05283_amd as cp
+    from oracle import refine as RF
+    from oracle import stepd as D
+    N, Np = 256, 6
+    scan = make_scan(1, N=N, Np=Np)
+    banner("refine volume N=256")
+    plan = cp.Plan(N, Np, theta=scan["theta"], n_ei=2, seed=scan["phase_seed"])
+    plan.submit(0, torch.from_numpy(scan["I"]).cuda(), torch.from_numpy(scan["support"]).cuda())
+    plan.iterate(2, cp.HIO, 0.9)
+    torch.cuda.synchronize()
+    obj = plan.objects().cpu().numpy().astype(np.float64)
+    got = plan.refine_volume(2).cpu().numpy()
+    banner("refine volume N=256: oracle")
+    E3, sampled = RF.measured_grid(obj, scan["theta"])
+    S3 = RF.support3d(scan["support"].astype(bool), scan["theta"])
+    ref, _ = RF.refine(D.assemble_volume(obj, scan["theta"]), E3, sampled, S3, 2)
+    r = rel_l2(got, ref)
+    print(f"refine N=256, 2 iterations: {r:.2e}")
+    assert r <= 1e-4
+    assert np.all(got[~S3] == 0)
+
+
+@pytest.mark.parametrize("real", [F32, F64])
+def test_refine_volume_n512_sampled(torch, real):
+    """N = 512, the size the benchmark times, at sampled voxels.  The step-D volume V0 is the real
+    part of the inverse transform of the inserted spectrum, so its spectrum equals the Hermitian
+    part of the inserted spectrum on the constrained cells and zero elsewhere, and the Fourier
+    replacement leaves it unchanged: one refinement iteration gives exactly P_S(V0), V0 kept on
+    the back-projected support where it is >= 0.  That value is evaluated voxel by voxel from the
+    definitions (V0 by the direct inverse DFT over the occupied cells).  The plane transforms of
+    the refinement run in full, so a wrong decomposition fails here.  Three more iterations are
+    checked for the properties that hold at any size: finite, zero outside the support, >= 0."""
+    import paper_2402_05283_amd as cp
+    from oracle import refine as RF
+    from oracle import stepd as D
+    N, Np = 512, 3
+    scan = make_scan(1, N=N, Np=Np)
+    banner(f"refine volume N=512 real={real}")
+    plan = cp.Plan(N, Np, theta=scan["theta"], n_ei=2, real=real, seed=scan["phase_seed"])
+    plan.submit(0, torch.from_numpy(scan["I"]).cuda(), torch.from_numpy(scan["support"]).cuda())
+    plan.iterate(2, cp.HIO, 0.9)
+    torch.cuda.synchronize()
+    obj = plan.objects().cpu().numpy().astype(np.float64)
+    v1 = plan.refine_volume(1)
+    rng = np.random.default_rng(5120)
+    S3 = RF.support3d(scan["support"].astype(bool), scan["theta"])
+    inside = np.argwhere(S3)
+    pts = np.concatenate([inside[rng.integers(0, len(inside), size=40)], rng.integers(0, N, size=(8, 3)),
+                          np.array([[N // 2] * 3])])
+    idx = torch.from_numpy(pts).long().cuda()
+    got = v1[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+    del v1
+    v0 = D.volume_at(obj, scan["theta"], pts)
+    keep = S3[pts[:, 0], pts[:, 1], pts[:, 2]]
+    want = np.where(keep & (v0 >= 0), v0, 0.0)
+    scale = np.abs(v0).max()
+    tol = (1e-4 if real == F32 else 1e-10) * scale
+    near = np.abs(v0) <= tol                              # the positivity decision is within rounding
+    ok = (np.abs(got - want) <= tol) | (near & ((np.abs(got) <= tol) | (np.abs(got - v0) <= tol)))
+    print(f"refine N=512 one iteration: max |diff| {np.abs(got - want).max() / scale:.2e} of max |V0|, "
+          f"{int(keep.sum())} voxels inside the support, {int(near.sum())} at the positivity edge")
+    assert keep.sum() >= 30 and np.all(ok)
+    banner(f"refine volume N=512 real={real}: three iterations")
+    v3 = plan.refine_volume(3)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(v3).all())
+    assert float(v3.min()) >= 0.0
+    s3 = torch.from_numpy(S3).cuda()
+    assert float(v3[~s3].abs().max()) == 0.0
+    assert float(v3.abs().max()) > 0.0
+
+
 def test_refine_needs_an_episode_end(torch):
     import paper_2402_05283_amd as cp
     scan = make_scan(1, Np=4)
