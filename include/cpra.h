@@ -310,6 +310,22 @@ cpra_status cpra_refine_workspace_size(const cpra_params* params, size_t* bytes)
 cpra_status cpra_refine_volume(cpra_plan_t plan, int32_t n_iter, int32_t shrink_every, double sigma,
                                double threshold, void* work, size_t work_bytes, void* d_volume);
 
+/*
+ * cpra_refine_volume without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, computation,
+ * results and errors as cpra_refine_volume; its scratch is a fixed 40 MiB
+ * device array inside the library (one copy per GPU, held until the process
+ * ends), enough for N <= 128 with F32 plans and N <= 64 with F64 plans;
+ * larger plans return CPRA_ERR_UNSUPPORTED.  The scratch starts with no
+ * required contents (every kernel writes what it reads).  Calls on one GPU
+ * share that array: two calls whose device work overlaps (different
+ * streams, or different host threads) race and give undefined results.
+ * Calls no hipMalloc, hipFree or other allocating device routine.
+ */
+cpra_status cpra_refine_volume_noalloc(cpra_plan_t plan, int32_t n_iter, int32_t shrink_every, double sigma,
+                                       double threshold, void* d_volume);
+
 /* Free the plan's host memory.  The workspace stays the caller's. */
 cpra_status cpra_destroy(cpra_plan_t plan);
 

@@ -31,6 +31,7 @@ EXPORTED = [
     "cpra_coupling_table", "cpra_set_kernel_timing", "cpra_kernel_timing", "cpra_load_objects",
     "cpra_iterate_batch", "cpra_prereconstruct", "cpra_sweep", "cpra_merge", "cpra_shrinkwrap",
     "cpra_read_support", "cpra_refine_workspace_size", "cpra_refine_volume", "cpra_set_graphs", "cpra_set_chunk",
+    "cpra_refine_volume_noalloc",
 ]
 
 
@@ -92,6 +93,8 @@ def load():
     lib.cpra_refine_workspace_size.argtypes = [P(Params), P(c.c_size_t)]
     lib.cpra_refine_volume.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_double, c.c_double, c.c_void_p,
                                        c.c_size_t, c.c_void_p]
+    lib.cpra_refine_volume_noalloc.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_double, c.c_double,
+                                               c.c_void_p]
     lib.cpra_last_error.argtypes = [c.c_void_p]
     lib.cpra_last_error.restype = c.c_char_p
     lib.cpra_iteration_count.argtypes = [c.c_void_p, P(c.c_int64)]
@@ -291,6 +294,15 @@ class Plan:
         _check(load().cpra_refine_volume(self.handle, int(n_iter), int(shrink_every), float(sigma), float(threshold),
                                          ctypes.c_void_p(wp), n.value, ctypes.c_void_p(out.data_ptr())), self.handle)
         self._leave(out, work)
+        return out
+
+    def refine_volume_noalloc(self, n_iter, out, shrink_every=0, sigma=1.0, threshold=0.1):
+        """cpra_refine_volume_noalloc into the caller's (N, N, N) volume `out` (no device allocation
+        here or in the library)."""
+        self._enter()
+        _check(load().cpra_refine_volume_noalloc(self.handle, int(n_iter), int(shrink_every), float(sigma),
+                                                 float(threshold), ctypes.c_void_p(out.data_ptr())), self.handle)
+        self._leave(out)
         return out
 
     def support(self):

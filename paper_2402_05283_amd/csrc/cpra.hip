@@ -30,6 +30,14 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Fixed device-resident scratch of cpra_refine_volume_noalloc (every GPU the library runs on holds
+// its own copy until the process ends).  Host code never uses the array's name as an address: its
+// device address is looked up once per device at plan creation (scratch_init) and kept in
+// g_scratch.  Every call on one GPU shares the array.
+constexpr size_t kScratchBytes = 40ull << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
 
 // row-pass mode of a real-space update rule (episode estimates use mode 2)
 int mode_of(int32_t algo) { return algo == CPRA_HIO ? 1 : algo == CPRA_RAAR ? 4 : 2; }
@@ -176,6 +184,29 @@ Layout layout_of(const cpra_params* p) {
 
 }  // namespace
 
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+// Look up this device's address of `scratch` (the current device must be the plan's); once per
+// device.  Returns the HIP error of the lookup.
+hipError_t scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[dev]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch[dev] = reinterpret_cast<char*>(ptr);
+  return e;
+}
+
+char* scratch_of(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[dev];
+}
+
+}  // namespace
 
 namespace {
 
@@ -311,9 +342,16 @@ cpra_status cpra_plan(const cpra_params* params, void* workspace, size_t workspa
   pl->landed.assign(params->Np, 0);
   pl->present.assign(params->Np, 0);
   pl->ntiles = col_tiles(params->N);
+  hipError_t e = hipGetDevice(&pl->device);
+  if (e == hipSuccess) e = scratch_init(pl->device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("plan setup (device scratch): ") + hipGetErrorString(e);
+    delete pl;
+    return CPRA_ERR_DEVICE;
+  }
   Ops ops = ops_of(pl->p);
   ops.twiddles(pl);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e == hipSuccess) e = hipMemsetAsync(pl->ws + L.flags, 0, 256, pl->stream);
   // angles not submitted yet read back as zero objects
   if (e == hipSuccess) e = hipMemsetAsync(pl->ws + L.g0, 0, L.A2 - L.g0, pl->stream);
@@ -935,7 +973,7 @@ cpra_status cpra_refine_workspace_size(const cpra_params* params, size_t* bytes)
   return CPRA_OK;
 }
 
-// the refinement on the scratch buffer `work` of work_bytes
+// the refinement on the scratch buffer `work` of work_bytes (the caller's, or the fixed device array)
 static cpra_status refine_run(cpra_plan_t pl, int32_t n_iter, int32_t shrink_every, double sigma, double threshold,
                               void* work, size_t work_bytes, void* d_volume) {
   if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
@@ -1014,6 +1052,19 @@ static cpra_status refine_run(cpra_plan_t pl, int32_t n_iter, int32_t shrink_eve
 cpra_status cpra_refine_volume(cpra_plan_t pl, int32_t n_iter, int32_t shrink_every, double sigma, double threshold,
                                void* work, size_t work_bytes, void* d_volume) {
   return refine_run(pl, n_iter, shrink_every, sigma, threshold, work, work_bytes, d_volume);
+}
+
+cpra_status cpra_refine_volume_noalloc(cpra_plan_t pl, int32_t n_iter, int32_t shrink_every, double sigma,
+                                       double threshold, void* d_volume) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  const size_t need = refine_layout(&pl->p).total;
+  if (need > kScratchBytes)
+    return fail(pl, CPRA_ERR_UNSUPPORTED,
+                "the fixed refinement scratch holds %zu bytes; N=%d with this real type needs %zu "
+                "(use cpra_refine_volume with a caller workspace)", kScratchBytes, pl->p.N, need);
+  char* w = scratch_of(pl->device);
+  if (!w) return fail(pl, CPRA_ERR_STATE, "no scratch address for device %d", pl->device);
+  return refine_run(pl, n_iter, shrink_every, sigma, threshold, w, kScratchBytes, d_volume);
 }
 
 cpra_status cpra_read_support(cpra_plan_t pl, uint8_t* out) {

@@ -32,6 +32,7 @@ struct cpra_plan_s {
   cpra_impl::Layout L{};
   char* ws = nullptr;
   hipStream_t stream = nullptr;
+  int device = 0;              // HIP device the plan was created on
   int cur = 0;                 // which g buffer holds the current iterate
   int64_t k = 0;               // global iteration count
   std::vector<uint8_t> landed, present;
