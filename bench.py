@@ -250,41 +250,90 @@ def summarize_trace(trace_dir, bench_json, cmd):
     return "\n".join(lines) + "\n"
 
 
-def serving_latency(cp, torch, scan, I, S, args):
-    """Last-frame-to-volume latency under the serving loop: `serve_scans` scans of the same shape
-    (N=512, Np=360; the bench scan's frames, a different phase seed each) open 0.25 s apart in each
-    round, rounds one scan-duration apart; frames land at serve_fps per scan in angle order; each
-    landed frame earns 10 iterations (one episode), the last one 50 more, then step D."""
+def serving_sources(torch, scan512, cache):
+    """Frame sources of the serving mix, as device tensors (I, S) per (N, Np): the benchmark's
+    512^3 cell scan with Poisson noise at 1e6 photons peak, the 256^3 polyhedron scan (Poisson 1e6)
+    and a 1024 scan of five ellipsoids (Poisson 1e6).  A 180-angle scan of N = 256 or 512 takes the
+    even angles of the 360-angle scan (the same angles pi n / 180).  The 1024 source has 180
+    angles only: its projections at 1024^2 take minutes of host time per 360 angles."""
+    from synth import make_scan
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(4000 + 1)
+    I = scan512["I"].astype(np.float64)
+    peak = 1e6 / I.reshape(I.shape[0], -1).max(axis=1)
+    I512 = rng.poisson(I * peak[:, None, None]).astype(np.float32)
+    if 256 not in cache:
+        print("[bench] serving: generating the N=256 source scan", file=sys.stderr, flush=True)
+        cache[256] = make_scan(2, N=256, Np=360)
+    print("[bench] serving: generating the N=1024 source scan", file=sys.stderr, flush=True)
+    s1024 = make_scan(1, N=1024, Np=180, peak=1e6)
+    src = {}
+    for n, (Iv, Sv) in ((512, (I512, scan512["support"])), (256, (cache[256]["I"], cache[256]["support"]))):
+        It, St = torch.from_numpy(Iv).to(dev), torch.from_numpy(Sv).to(dev)
+        src[(n, 360)] = (It, St)
+        src[(n, 180)] = (It[0::2].contiguous(), St[0::2].contiguous())
+    src[(1024, 180)] = (torch.from_numpy(s1024["I"]).to(dev), torch.from_numpy(s1024["support"]).to(dev))
+    return src
+
+
+def serving_latency(cp, torch, scan, I, S, args, cache):
+    """Last-frame-to-volume latency under the serving loop on a mix of scan shapes: `serve_scans`
+    detector lanes, each delivering scans back to back (0.25 s apart, lanes staggered by 0.25 s);
+    every scan's shape is drawn (seeded) from N in {256, 512, 1024} and N_p in {180, 360} (N = 1024
+    with 180 only), its frames land at serve_fps in angle order; each landed frame earns 10 HIO
+    iterations on the partial angle set (one episode), the last one 50 more, then step D.  The
+    scans of all lanes that are open at a time are served together (continuous batching)."""
     from paper_2402_05283_amd import serve
-    T = NP / args.serve_fps
+    src = serving_sources(torch, scan, cache)
+    rng = np.random.default_rng(5)
     jobs = []
-    for r in range(args.serve_rounds):
-        for i in range(args.serve_scans):
-            jobs.append(serve.Job(r * T + 0.25 * i, N, NP, (lambda n: (I[n:n + 1], S[n:n + 1])), args.serve_fps,
-                                  seed=scan["phase_seed"] + 1 + r * args.serve_scans + i))
+    for lane in range(args.serve_scans):
+        t = 0.25 * lane
+        for i in range(args.serve_per_lane):
+            n = int(rng.choice([256, 512, 1024]))
+            npp = 180 if n == 1024 else int(rng.choice([180, 360]))
+            It, St = src[(n, npp)]
+            jobs.append(serve.Job(t, n, npp, (lambda k, It=It, St=St: (It[k:k + 1], St[k:k + 1])), args.serve_fps,
+                                  seed=scan["phase_seed"] + 1 + len(jobs), theta=np.pi * np.arange(npp) / npp))
+            t += npp / args.serve_fps + 0.25
+    T = max(j.t_start + j.Np / j.fps for j in jobs)
     srv = serve.Server(200 << 30, n_ei=N_EI, r_frame=N_EI, r_final=50, algo=cp.HIO, beta=BETA)
-    print(f"[bench] serving {len(jobs)} scans at {args.serve_fps} frames/s each "
-          f"(~{T * args.serve_rounds + 0.25 * args.serve_scans:.0f} s)", file=sys.stderr, flush=True)
+    prev_fuse = cp.set_batch_fusion(args.serve_fusion) if args.serve_fusion is not None else None
+    print(f"[bench] serving {len(jobs)} scans on {args.serve_scans} lanes at {args.serve_fps} frames/s each "
+          f"(~{T:.0f} s)", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     count = [0]
 
     def on_done(sc):
         count[0] += 1
-        print(f"[bench] serving: {count[0]}/{len(jobs)} scans done, last-frame-to-volume "
+        print(f"[bench] serving: {count[0]}/{len(jobs)} scans done (N={sc.N} Np={sc.Np}), last-frame-to-volume "
               f"{sc.latency_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
     done = serve.replay(srv, jobs, on_done=on_done)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    fuse = cp.get_batch_fusion()
+    if prev_fuse is not None:
+        cp.set_batch_fusion(prev_fuse)
     lat = np.array([d.latency_s for d in done]) * 1e3
-    work = sum(d.iters_done for d in done)
+    work = sum(d.iters_done * d.Np for d in done)
     print(f"[bench] serving done in {wall:.1f} s; latency p50 {np.percentile(lat, 50):.1f} ms, "
           f"max {lat.max():.1f} ms", file=sys.stderr, flush=True)
+    by_shape = {}
+    for d, l in zip(done, lat):
+        by_shape.setdefault(f"N={d.N},Np={d.Np}", []).append(l)
+    del src
+    torch.cuda.empty_cache()
     return {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
             "max": round(float(lat.max()), 2), "samples": int(lat.size),
-            "what": f"last frame to volume ready: {args.serve_scans} concurrent N={N} Np={NP} scans per round, "
-                    f"{args.serve_rounds} round(s), {args.serve_fps:g} frames/s each, 10 HIO iterations per landed "
-                    f"frame (partial angle sets), 50 after the last, then step D",
-            "serving_wall_s": round(wall, 2), "scan_iterations": int(work)}
+            "by_shape": {k: {"samples": len(v), "p50": round(float(np.percentile(v, 50)), 2),
+                             "p99": round(float(np.percentile(v, 99)), 2)} for k, v in sorted(by_shape.items())},
+            "what": f"last frame to volume ready: {args.serve_scans} lanes of scans back to back, shapes drawn from "
+                    f"N in {{256, 512, 1024}}, N_p in {{180, 360}} (1024 with 180), Poisson 1e6 data, "
+                    f"{args.serve_fps:g} frames/s per scan, 10 HIO iterations per landed frame (partial angle sets), "
+                    f"50 after the last, then step D",
+            "shared_launches_up_to_N": fuse,
+            "serving_wall_s": round(wall, 2), "pattern_iterations": int(work),
+            "pattern_iterations_per_s": round(work / wall, 1)}
 
 
 class Quality:
@@ -537,7 +586,7 @@ def variants(cp, torch, scan, I, S, args):
     return out
 
 
-def batched_scans(cp, torch, scan512, args):
+def batched_scans(cp, torch, scan512, args, cache):
     """Config-3-like batch: 48 scans of uneven size (N drawn from {128, 192, 256, 384, 512}, N_p
     from [90, 360], seeded), 300 HIO iterations each, advanced together through
     cpra_iterate_batch (every plan on its own stream), against the same plans iterated one after
@@ -550,7 +599,9 @@ def batched_scans(cp, torch, scan512, args):
     src = {512: scan512}
     for n in sorted(set(int(x) for x in sizes) - {512}):
         print(f"[bench] batched: generating the N={n} source scan", file=sys.stderr, flush=True)
-        src[n] = make_scan(2 if n >= 256 else 1, N=n, Np=360)
+        if n not in cache:
+            cache[n] = make_scan(2 if n >= 256 else 1, N=n, Np=360)
+        src[n] = cache[n]
     dev = torch.device("cuda", 0)
     data = {n: (torch.from_numpy(s["I"]).to(dev), torch.from_numpy(s["support"]).to(dev), s["theta"])
             for n, s in src.items()}
@@ -578,20 +629,31 @@ def batched_scans(cp, torch, scan512, args):
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     del plans
-    rng_sub = np.random.default_rng(4)
-    streams = [torch.cuda.Stream() for _ in sizes]
-    plans = make_plans(streams)
-    t0 = time.perf_counter()
-    cp.iterate_batch(plans, iters, cp.HIO, BETA)
-    torch.cuda.synchronize()
-    t_bat = time.perf_counter() - t0
-    del plans
-    torch.cuda.empty_cache()
+    t_bat = {}
+    for fuse in (0, 256, 1024):
+        rng_sub = np.random.default_rng(4)
+        streams = [torch.cuda.Stream() for _ in sizes]
+        plans = make_plans(streams)
+        prev = cp.set_batch_fusion(fuse)
+        t0 = time.perf_counter()
+        cp.iterate_batch(plans, iters, cp.HIO, BETA)
+        torch.cuda.synchronize()
+        t_bat[fuse] = time.perf_counter() - t0
+        cp.set_batch_fusion(prev)
+        del plans
+        torch.cuda.empty_cache()
+    best = min(t_bat, key=t_bat.get)
     return {"scans": int(args.batch_scans), "iterations": iters, "pattern_iterations": work,
             "sizes": {int(n): int((sizes == n).sum()) for n in sorted(set(int(x) for x in sizes))},
-            "batched_s": round(t_bat, 3), "sequential_s": round(t_seq, 3),
-            "batched_pattern_iterations_per_s": round(work / t_bat, 1),
-            "sequential_pattern_iterations_per_s": round(work / t_seq, 1)}
+            "batched_s": round(t_bat[best], 3), "sequential_s": round(t_seq, 3),
+            "batched_pattern_iterations_per_s": round(work / t_bat[best], 1),
+            "sequential_pattern_iterations_per_s": round(work / t_seq, 1),
+            "by_fusion": {f"fuse_N<={k}": {"s": round(v, 3), "pattern_iterations_per_s": round(work / v, 1)}
+                          for k, v in t_bat.items()},
+            "what": "cpra_iterate_batch over all 48 plans, each on its own stream; plans of one size class with "
+                    "N <= the fusion limit share one launch per pass per iteration (limit 0: every plan's "
+                    "launches interleaved on its own stream); batched_s is the best limit; sequential: "
+                    "cpra_iterate on each plan in turn"}
 
 
 def fp16_leg(cp, torch, scan, I, S, vol, stream, args, steps=3):
@@ -661,9 +723,13 @@ def main():
     ap.add_argument("--amp16", action="store_true", help="FP16 amplitude storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters", type=int, default=ITERS)
-    ap.add_argument("--serve-scans", type=int, default=8, help="concurrent scans in the serving leg (0: skip)")
-    ap.add_argument("--serve-rounds", type=int, default=1, help="serving rounds (latency samples = scans x rounds)")
+    ap.add_argument("--serve-scans", type=int, default=8, help="detector lanes of the serving leg (0: skip)")
+    ap.add_argument("--serve-per-lane", type=int, default=13,
+                    help="scans per lane (latency samples = lanes x scans per lane)")
     ap.add_argument("--serve-fps", type=float, default=20.0, help="frames per second per scan")
+    ap.add_argument("--serve-fusion", type=int, default=None,
+                    help="size limit of shared launches in the serving leg (cpra_set_batch_fusion; default: "
+                         "the library's)")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain per-angle comparison")
     ap.add_argument("--guesses", type=int, default=100, help="N_r of the paper-schedule leg (0: skip it)")
     ap.add_argument("--batch-scans", type=int, default=48, help="scans of the uneven-size batch leg (0: skip)")
@@ -722,6 +788,7 @@ def main():
     col_n = row_n = 0
     lat = []
     qcache = []
+    src_cache = {}      # synthetic source scans shared by the batch and serving legs
 
     def quality_of():
         if not qcache:
@@ -817,9 +884,9 @@ def main():
         out["paper_schedule"] = paper_schedule(cp, torch, scan, I, S, args, quality_of())
     if args.batch_scans > 0 and args.iters == ITERS and not args.amp16:
         print(f"[bench] batched: {args.batch_scans} scans of uneven size", file=sys.stderr, flush=True)
-        out["batched_uneven_scans"] = batched_scans(cp, torch, scan, args)
+        out["batched_uneven_scans"] = batched_scans(cp, torch, scan, args, src_cache)
     if args.serve_scans > 0:
-        out["latency_ms"] = serving_latency(cp, torch, scan, I, S, args)
+        out["latency_ms"] = serving_latency(cp, torch, scan, I, S, args, src_cache)
         out["latency_ms"]["whole_scan_p50"] = round(float(np.percentile(lat, 50)) * 1e3, 2)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)

@@ -50,7 +50,7 @@ enum { CPRA_INSERT_NEAREST = 0, CPRA_INSERT_BILINEAR = 1 };   /* step D insertio
 enum { CPRA_WRAP_MIRROR = 0, CPRA_WRAP_PLAIN = 1 };  /* carousel seam rule    */
 enum { CPRA_REAL_F32 = 0, CPRA_REAL_F64 = 1 };       /* arithmetic precision  */
 enum { CPRA_AMP_F32 = 0, CPRA_AMP_F16 = 1 };         /* amplitude storage     */
-enum { CPRA_PTR_HOST = 0, CPRA_PTR_DEVICE = 1 };
+enum { CPRA_PTR_HOST = 0, CPRA_PTR_DEVICE = 1, CPRA_PTR_DEVICE_ASYNC = 2 };
 
 typedef struct {
   uint32_t struct_size;  /* = sizeof(cpra_params)                                     */
@@ -106,12 +106,21 @@ cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t 
  * the maps of angles [first, first+count).  intensity: count x N x N float,
  * centred [n][w][u]; support: count x N x N uint8 (nonzero = inside),
  * centred [n][z][t].  Both on the host (CPRA_PTR_HOST: copied before the
- * call returns) or on the device (CPRA_PTR_DEVICE: read in stream order).
+ * call returns) or on the device (CPRA_PTR_DEVICE, CPRA_PTR_DEVICE_ASYNC:
+ * read in stream order).
  * Computes A = sqrt(I), packs the support, and draws each angle's random
  * initial PO (W_0): Re F2^-1(A exp(i phi)), phi from SplitMix64(seed) at
  * counter (n*N + w)*N + u.  An angle may be submitted once.  An angle that
  * arrives mid-episode waits and joins at the next episode boundary.
- * Synchronises the stream (to report ERR_DATA).
+ * CPRA_PTR_HOST and CPRA_PTR_DEVICE synchronise the stream and return
+ * ERR_DATA (nothing submitted) if the intensities hold a NaN or Inf.
+ * CPRA_PTR_DEVICE_ASYNC (for a serving loop that must not wait on the GPU)
+ * does not synchronise with plans of one guess: the angles count as
+ * submitted at once, and the NaN/Inf check completes in stream order; the
+ * first call on the plan after it completes (submit, iterate, iterate_batch,
+ * read_objects, assemble_volume) returns ERR_DATA if it failed, and the plan
+ * is then poisoned.  The device inputs must stay valid until the stream has
+ * consumed them.
  */
 cpra_status cpra_submit_angles(cpra_plan_t plan, int32_t first, int32_t count,
                                const float* intensity, const uint8_t* support, int32_t ptr_kind);
@@ -213,17 +222,35 @@ cpra_status cpra_set_chunk(cpra_plan_t plan, int32_t slots);
  * and C over scans rather than angles): `count` distinct plans, possibly of
  * different N and Np, each advance n_iter iterations with the same algo and
  * beta.  Each plan's episode phase follows its own k, exactly as
- * cpra_iterate would.  The iterations are issued interleaved, iteration by
- * iteration and plan by plan, each on its own plan's stream, so plans on
- * different streams overlap on the device.  Results are those of calling
- * cpra_iterate on each plan alone.  No error history is returned (use
- * cpra_iterate for that).  Checks every plan first: NULL array, NULL or
- * repeated plans, a poisoned plan, or a plan with no angle return
- * ERR_ARG / ERR_STATE and no plan advances.  A device error poisons the
- * plan it occurred in and returns ERR_DEVICE; the others stay usable.
- * Asynchronous.
+ * cpra_iterate would.  Plans of one size class (same N, real type and
+ * amplitude type) with three-tap coupling and launch-by-launch episodes
+ * share launches: per iteration, one column-pass and one row-pass launch
+ * over the listed slots of up to 16 such plans (more launches only when the
+ * plans stand at different points of their episodes), issued on the first
+ * plan's stream, which is ordered after every plan's stream before and
+ * before every plan's stream after.  Other plans advance interleaved,
+ * iteration by iteration, each on its own stream.  Results are those of
+ * calling cpra_iterate on each plan alone, bit for bit.  No error history is
+ * returned (use cpra_iterate for that).  Checks every plan first: NULL
+ * array, NULL or repeated plans, a poisoned plan, or a plan with no angle
+ * return ERR_ARG / ERR_STATE and no plan advances.  A device error poisons
+ * the plan it occurred in and returns ERR_DEVICE; the others stay usable.
+ * Asynchronous, except where a plan's angle set changes at a boundary (its
+ * coupling tables are uploaded and the stream synchronised).
  */
 cpra_status cpra_iterate_batch(cpra_plan_t* plans, int32_t count, int32_t n_iter, int32_t algo, double beta);
+
+/*
+ * Process-wide choice of the size classes whose plans share launches in
+ * cpra_iterate_batch: those with N <= max_n (0: none; the library's default
+ * is given in its documentation of measurements).  Plans outside advance
+ * on their own streams with their own launches; results are identical
+ * either way.  ERR_ARG if max_n < 0.
+ */
+cpra_status cpra_set_batch_fusion(int32_t max_n);
+
+/* The current setting of cpra_set_batch_fusion (host only). */
+cpra_status cpra_get_batch_fusion(int32_t* max_n);
 
 /*
  * Shrinkwrap support update (the conventional 2D shrinkwrap step, run by
@@ -326,7 +353,8 @@ cpra_status cpra_refine_volume(cpra_plan_t plan, int32_t n_iter, int32_t shrink_
 cpra_status cpra_refine_volume_noalloc(cpra_plan_t plan, int32_t n_iter, int32_t shrink_every, double sigma,
                                        double threshold, void* d_volume);
 
-/* Free the plan's host memory.  The workspace stays the caller's. */
+/* Free the plan's host memory.  The workspace stays the caller's.  In a process forked
+   after the plan was created, only the host bookkeeping is dropped (no HIP call). */
 cpra_status cpra_destroy(cpra_plan_t plan);
 
 /* Last error message of the plan (or of the last failed create if plan is NULL). */

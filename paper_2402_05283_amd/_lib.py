@@ -23,7 +23,7 @@ INSERT_NEAREST, INSERT_BILINEAR = 0, 1
 WRAP_MIRROR, WRAP_PLAIN = 0, 1
 REAL_F32, REAL_F64 = 0, 1
 AMP_F32, AMP_F16 = 0, 1
-PTR_HOST, PTR_DEVICE = 0, 1
+PTR_HOST, PTR_DEVICE, PTR_DEVICE_ASYNC = 0, 1, 2
 
 EXPORTED = [
     "cpra_workspace_size", "cpra_plan", "cpra_plan_create", "cpra_submit_angles", "cpra_iterate", "cpra_read_objects",
@@ -31,7 +31,7 @@ EXPORTED = [
     "cpra_coupling_table", "cpra_set_kernel_timing", "cpra_kernel_timing", "cpra_load_objects",
     "cpra_iterate_batch", "cpra_prereconstruct", "cpra_sweep", "cpra_merge", "cpra_shrinkwrap",
     "cpra_read_support", "cpra_refine_workspace_size", "cpra_refine_volume", "cpra_set_graphs", "cpra_set_chunk",
-    "cpra_refine_volume_noalloc",
+    "cpra_refine_volume_noalloc", "cpra_set_batch_fusion", "cpra_get_batch_fusion",
 ]
 
 
@@ -95,6 +95,8 @@ def load():
                                        c.c_size_t, c.c_void_p]
     lib.cpra_refine_volume_noalloc.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_double, c.c_double,
                                                c.c_void_p]
+    lib.cpra_set_batch_fusion.argtypes = [c.c_int32]
+    lib.cpra_get_batch_fusion.argtypes = [P(c.c_int32)]
     lib.cpra_last_error.argtypes = [c.c_void_p]
     lib.cpra_last_error.restype = c.c_char_p
     lib.cpra_iteration_count.argtypes = [c.c_void_p, P(c.c_int64)]
@@ -114,6 +116,22 @@ def _check(st, plan=None):
     if st != CPRA_OK:
         msg = load().cpra_last_error(plan)
         raise CpraError(st, msg.decode() if msg else "")
+
+
+def get_batch_fusion():
+    """cpra_get_batch_fusion: the size limit of shared launches in iterate_batch."""
+    v = ctypes.c_int32(0)
+    _check(load().cpra_get_batch_fusion(ctypes.byref(v)))
+    return v.value
+
+
+def set_batch_fusion(max_n):
+    """cpra_set_batch_fusion: plans of one size class with N <= max_n share launches in
+    iterate_batch (0: none).  Returns the previous setting."""
+    prev = ctypes.c_int32(0)
+    _check(load().cpra_get_batch_fusion(ctypes.byref(prev)))
+    _check(load().cpra_set_batch_fusion(int(max_n)))
+    return prev.value
 
 
 def iterate_batch(plans, n_iter, algo=HIO, beta=0.9):
@@ -199,6 +217,7 @@ class Plan:
         self._ws_ptr = (base + 255) // 256 * 256
         self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
         handle = ctypes.c_void_p(0)
+        self._pid = os.getpid()
         st = lib.cpra_plan(ctypes.byref(self.params), ctypes.c_void_p(self._ws_ptr), nbytes,
                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle))
         _check(st, None)
@@ -222,12 +241,17 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        # a forked child process (a worker pool) holds a copy of the object but not the GPU state:
+        # only the creating process destroys the plan
+        if h is not None and h.value and getattr(self, "_pid", None) == os.getpid():
             load().cpra_destroy(h)
             self.handle = None
 
-    def submit(self, first, intensity, support):
-        """intensity: (count,N,N) float32; support: (count,N,N) uint8 — torch CUDA tensors or numpy arrays."""
+    def submit(self, first, intensity, support, asynchronous=False):
+        """intensity: (count,N,N) float32; support: (count,N,N) uint8 — torch CUDA tensors or numpy arrays.
+        asynchronous (CUDA tensors): the library does not wait for the GPU; a NaN/Inf in the
+        intensities is reported by a later call (and poisons the plan); the tensors are kept alive
+        for the plan's stream."""
         torch = self.torch
         if isinstance(intensity, np.ndarray):
             I = np.ascontiguousarray(intensity, dtype=np.float32)
@@ -240,9 +264,11 @@ class Plan:
             if I.dtype != torch.float32 or S.dtype != torch.uint8 or not I.is_cuda or not S.is_cuda:
                 raise TypeError("device inputs must be CUDA float32 intensity and uint8 support")
             count = I.shape[0]
-            self._enter()       # the library reads I and S on its stream and synchronises before returning
+            self._enter()       # the library reads I and S on its stream
             st = load().cpra_submit_angles(self.handle, first, count, ctypes.c_void_p(I.data_ptr()),
-                                           ctypes.c_void_p(S.data_ptr()), PTR_DEVICE)
+                                           ctypes.c_void_p(S.data_ptr()), PTR_DEVICE_ASYNC if asynchronous else PTR_DEVICE)
+            if asynchronous and st == CPRA_OK:
+                self._leave(I, S)
         _check(st, self.handle)
 
     def iterate(self, n_iter, algo=HIO, beta=0.9, errors=False):

@@ -43,6 +43,10 @@ char* g_scratch[kMaxDevices] = {};
 int mode_of(int32_t algo) { return algo == CPRA_HIO ? 1 : algo == CPRA_RAAR ? 4 : 2; }
 
 thread_local std::string g_create_error;
+// cpra_iterate_batch shares launches between plans of one size class when N <= this
+// (cpra_set_batch_fusion; 0: never, the default: on uneven batches the plans' own launches
+// interleaved over their streams measured faster than shared launches)
+int g_fuse_max_n = 0;
 
 
 bool size_supported(int N) {
@@ -162,12 +166,14 @@ Layout layout_of(const cpra_params* p) {
   L.tw = take((3 * N + 3 * H) * cs);   // twiddle tables (kernels.hpp, TwLayout)
   L.coup = take(S * sizeof(cpra::Coupling));
   L.alist = take(S * 4);
+  L.iota = take(S * 4);                                            // 0 .. S-1
   L.errpart = take((size_t)kErrSlots * S * col_tiles(p->N) * 8);
   L.errhist = take((size_t)kErrSlots * S * 8);
   L.flags = take(256);
   L.stage_I = take((size_t)kStageAngles * N * N * 4);
   L.stage_S = take((size_t)kStageAngles * N * N);
   L.csr_ptr = take((N * N + 1) * 4);
+  L.csr_cell = take(N * N * sizeof(cpra::CellRec));
   const size_t ents = Np * N * (p->insertion == CPRA_INSERT_BILINEAR ? 4 : 1);   // at most
   L.csr_ent = take(ents * 4);
   L.csr_w = take(p->insertion == CPRA_INSERT_BILINEAR ? ents * rs : 0);
@@ -270,8 +276,18 @@ cpra_status upload_tables(cpra_plan_t pl) {
       pl->coup_h[(size_t)r * Np + n] = c;
       if (pl->present[n]) pl->alist_h.push_back(r * Np + n);
     }
-  HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.coup, pl->coup_h.data(), pl->coup_h.size() * sizeof(cpra::Coupling),
+  // the device tables are copied from the plan's pinned staging buffer, without synchronising the
+  // stream: the copies are ordered behind the launches that read the previous tables, and the
+  // staging buffer is rewritten only after the previous upload has completed (ev_tab)
+  if (pl->tab_pending) {
+    HIPCHK(pl, hipEventSynchronize(pl->ev_tab));
+    pl->tab_pending = false;
+  }
+  char* hb = reinterpret_cast<char*>(pl->h_tab);
+  std::memcpy(hb, pl->coup_h.data(), pl->coup_h.size() * sizeof(cpra::Coupling));
+  HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.coup, hb, pl->coup_h.size() * sizeof(cpra::Coupling),
                             hipMemcpyHostToDevice, pl->stream));
+  hb += align_up(pl->coup_h.size() * sizeof(cpra::Coupling));
   if (pl->K > 1) {   // Eq. 4 with 2K+1 taps: one table per guess ring
     std::vector<cpra_host::Tap> t1;
     cpra_host::tap_table(Np, pl->present.data(), pl->taps.data(), pl->K, pl->p.wrap == CPRA_WRAP_MIRROR, t1);
@@ -283,14 +299,17 @@ cpra_status upload_tables(cpra_plan_t pl) {
         t.nb += r * Np;
         pl->tap_h[(size_t)r * Np * nt + i] = t;
       }
-    HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.ctab, pl->tap_h.data(), pl->tap_h.size() * sizeof(cpra::Tap),
-                              hipMemcpyHostToDevice, pl->stream));
+    std::memcpy(hb, pl->tap_h.data(), pl->tap_h.size() * sizeof(cpra::Tap));
+    HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.ctab, hb, pl->tap_h.size() * sizeof(cpra::Tap), hipMemcpyHostToDevice,
+                              pl->stream));
+    hb += align_up(pl->tap_h.size() * sizeof(cpra::Tap));
   }
-  if (!pl->alist_h.empty())
-    HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist, pl->alist_h.data(), pl->alist_h.size() * 4,
-                              hipMemcpyHostToDevice, pl->stream));
-  // the host vectors are rewritten at the next boundary: make the copies complete first
-  HIPCHK(pl, hipStreamSynchronize(pl->stream));
+  if (!pl->alist_h.empty()) {
+    std::memcpy(hb, pl->alist_h.data(), pl->alist_h.size() * 4);
+    HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist, hb, pl->alist_h.size() * 4, hipMemcpyHostToDevice, pl->stream));
+  }
+  HIPCHK(pl, hipEventRecord(pl->ev_tab, pl->stream));
+  pl->tab_pending = true;
   pl->tables_dirty = false;
   pl->table_version += 1;
   return CPRA_OK;
@@ -339,6 +358,7 @@ cpra_status cpra_plan(const cpra_params* params, void* workspace, size_t workspa
   pl->L = L;
   pl->ws = reinterpret_cast<char*>(workspace);
   pl->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  pl->pid = (int)getpid();
   pl->landed.assign(params->Np, 0);
   pl->present.assign(params->Np, 0);
   pl->ntiles = col_tiles(params->N);
@@ -349,9 +369,22 @@ cpra_status cpra_plan(const cpra_params* params, void* workspace, size_t workspa
     delete pl;
     return CPRA_ERR_DEVICE;
   }
+  // pinned staging of the tables (coupling records, taps, slot list) and of the data-check flag
+  const size_t S = (size_t)params->Np * pl->R;
+  const size_t tab_bytes = align_up(S * sizeof(cpra::Coupling)) +
+                           align_up(pl->K > 1 ? S * (2 * pl->K + 1) * sizeof(cpra::Tap) : 0) + S * 4;
+  e = hipHostMalloc(&pl->h_tab, tab_bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&pl->h_flag, 256, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_tab, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_flag, hipEventDisableTiming);
+  std::vector<int32_t> iota(S);
+  std::iota(iota.begin(), iota.end(), 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(pl->ws + L.iota, iota.data(), S * 4, hipMemcpyHostToDevice, pl->stream);
   Ops ops = ops_of(pl->p);
-  ops.twiddles(pl);
-  e = hipGetLastError();
+  if (e == hipSuccess) {
+    ops.twiddles(pl);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) e = hipMemsetAsync(pl->ws + L.flags, 0, 256, pl->stream);
   // angles not submitted yet read back as zero objects
   if (e == hipSuccess) e = hipMemsetAsync(pl->ws + L.g0, 0, L.A2 - L.g0, pl->stream);
@@ -396,6 +429,17 @@ static cpra_status ensure_stepd_tables(cpra_plan_t pl) {
   }
   const Layout& L = pl->L;
   HIPCHK(pl, hipMemcpyAsync(pl->ws + L.csr_ptr, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, pl->stream));
+  // the cell records of step D's gather: first entry, entry range, inverse count as FP32 bits
+  pl->cell_h.resize(NN);
+  for (size_t c = 0; c < NN; ++c) {
+    cpra::CellRec& r = pl->cell_h[c];
+    r.begin = rp[c];
+    r.end = rp[c + 1];
+    r.first = rp[c] < rp[c + 1] ? ent[rp[c]] : -1;
+    std::memcpy(&r.inv_bits, &pl->inv_f[c], 4);
+  }
+  HIPCHK(pl, hipMemcpyAsync(pl->ws + L.csr_cell, pl->cell_h.data(), NN * sizeof(cpra::CellRec), hipMemcpyHostToDevice,
+                            pl->stream));
   HIPCHK(pl, hipMemcpyAsync(pl->ws + L.csr_ent, ent.data(), ent.size() * 4, hipMemcpyHostToDevice, pl->stream));
   if (bil) {
     if (f64) HIPCHK(pl, hipMemcpyAsync(pl->ws + L.csr_w, wts.data(), wts.size() * 8, hipMemcpyHostToDevice, pl->stream));
@@ -407,6 +451,20 @@ static cpra_status ensure_stepd_tables(cpra_plan_t pl) {
   return CPRA_OK;
 }
 
+// An asynchronous submit's data check: once its flag copy has landed, a NaN or Inf poisons the plan.
+static cpra_status check_data(cpra_plan_t pl) {
+  if (!pl->flag_pending) return CPRA_OK;
+  const hipError_t q = hipEventQuery(pl->ev_flag);
+  if (q == hipErrorNotReady) return CPRA_OK;
+  if (q != hipSuccess) return fail(pl, CPRA_ERR_DEVICE, "data check: %s", hipGetErrorString(q));
+  pl->flag_pending = false;
+  if (*pl->h_flag & 1) {
+    pl->poisoned = true;
+    return fail(pl, CPRA_ERR_DATA, "the intensity of an asynchronously submitted angle contains NaN or Inf");
+  }
+  return CPRA_OK;
+}
+
 cpra_status cpra_submit_angles(cpra_plan_t pl, int32_t first, int32_t count, const float* intensity,
                                const uint8_t* support, int32_t ptr_kind) {
   if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
@@ -414,18 +472,27 @@ cpra_status cpra_submit_angles(cpra_plan_t pl, int32_t first, int32_t count, con
   if (count < 1 || first < 0 || first + count > pl->p.Np)
     return fail(pl, CPRA_ERR_ARG, "angles [%d, %d) outside [0, %d)", first, first + count, pl->p.Np);
   if (!intensity || !support) return fail(pl, CPRA_ERR_ARG, "intensity/support is NULL");
-  if (ptr_kind != CPRA_PTR_HOST && ptr_kind != CPRA_PTR_DEVICE) return fail(pl, CPRA_ERR_ARG, "bad ptr_kind");
+  if (ptr_kind != CPRA_PTR_HOST && ptr_kind != CPRA_PTR_DEVICE && ptr_kind != CPRA_PTR_DEVICE_ASYNC)
+    return fail(pl, CPRA_ERR_ARG, "bad ptr_kind");
   for (int i = 0; i < count; ++i)
     if (pl->landed[first + i]) return fail(pl, CPRA_ERR_STATE, "angle %d was already submitted", first + i);
+  {
+    const cpra_status st = check_data(pl);
+    if (st != CPRA_OK) return st;
+  }
   const int N = pl->p.N;
   const size_t NN = (size_t)N * N;
+  const bool async = ptr_kind == CPRA_PTR_DEVICE_ASYNC;
   Ops ops = ops_of(pl->p);
-  HIPCHK(pl, hipMemsetAsync(pl->ws + pl->L.flags, 0, 4, pl->stream));
+  // the synchronous forms report this call's data check; the asynchronous form keeps the flag,
+  // which then covers every asynchronous submit since the last synchronous one
+  if (!async) HIPCHK(pl, hipMemsetAsync(pl->ws + pl->L.flags, 0, 4, pl->stream));
   // slots to initialise: every guess's copy of each submitted angle, grouped per staging chunk
   const int R = pl->R, Np = pl->p.Np;
   // host inputs are staged through the workspace a few angles at a time;
   // device inputs go out in one launch of each kernel
   const int chunk = ptr_kind == CPRA_PTR_HOST ? kStageAngles : count;
+  bool used_alist = false;
   for (int c0 = 0; c0 < count; c0 += chunk) {
     const int cn = std::min(chunk, count - c0);
     const float* dI;
@@ -441,23 +508,42 @@ cpra_status cpra_submit_angles(cpra_plan_t pl, int32_t first, int32_t count, con
     }
     ops.prep(pl, dI, dS, first + c0, cn);
     LAUNCHCHK(pl);
-    // initial objects of every guess go into the buffer that holds the current iterate
-    std::vector<int32_t> ids;
-    for (int r = 0; r < R; ++r)
-      for (int i = 0; i < cn; ++i) ids.push_back(r * Np + first + c0 + i);
-    HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, pl->stream));
-    ops.init(pl, at<int>(pl, pl->L.alist), (int)ids.size(), pl->cur);
-    LAUNCHCHK(pl);
-    HIPCHK(pl, hipStreamSynchronize(pl->stream));   // ids is rebuilt for the next chunk
+    // initial objects of every guess go into the buffer that holds the current iterate; with one
+    // guess the slots are consecutive and listed by the plan's fixed identity list
+    if (R == 1) {
+      ops.init(pl, at<int>(pl, pl->L.iota) + first + c0, cn, pl->cur);
+      LAUNCHCHK(pl);
+      if (ptr_kind == CPRA_PTR_HOST) HIPCHK(pl, hipStreamSynchronize(pl->stream));   // the staging buffers
+    } else {
+      std::vector<int32_t> ids;
+      for (int r = 0; r < R; ++r)
+        for (int i = 0; i < cn; ++i) ids.push_back(r * Np + first + c0 + i);
+      HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, pl->stream));
+      ops.init(pl, at<int>(pl, pl->L.alist), (int)ids.size(), pl->cur);
+      LAUNCHCHK(pl);
+      HIPCHK(pl, hipStreamSynchronize(pl->stream));   // ids is rebuilt for the next chunk
+      used_alist = true;
+    }
   }
-  int flag = 0;
-  HIPCHK(pl, hipMemcpyAsync(&flag, pl->ws + pl->L.flags, 4, hipMemcpyDeviceToHost, pl->stream));
-  HIPCHK(pl, hipStreamSynchronize(pl->stream));
-  pl->tables_dirty = true;   // alist was used as scratch
-  if (flag & 1) return fail(pl, CPRA_ERR_DATA, "intensity contains NaN or Inf");
+  if (async) {
+    // the flag travels to pinned host memory behind this submit's work; check_data reads it
+    HIPCHK(pl, hipMemcpyAsync(pl->h_flag, pl->ws + pl->L.flags, 4, hipMemcpyDeviceToHost, pl->stream));
+    HIPCHK(pl, hipEventRecord(pl->ev_flag, pl->stream));
+    pl->flag_pending = true;
+  } else {
+    int flag = 0;
+    HIPCHK(pl, hipMemcpyAsync(&flag, pl->ws + pl->L.flags, 4, hipMemcpyDeviceToHost, pl->stream));
+    HIPCHK(pl, hipStreamSynchronize(pl->stream));
+    if (used_alist) pl->tables_dirty = true;   // alist was used as scratch
+    if (flag & 1) {
+      HIPCHK(pl, hipMemsetAsync(pl->ws + pl->L.flags, 0, 4, pl->stream));
+      return fail(pl, CPRA_ERR_DATA, "intensity contains NaN or Inf");
+    }
+  }
   for (int i = 0; i < count; ++i) pl->landed[first + i] = 1;
-  if (pl->k % pl->p.n_ei == 0) {
+  if (pl->k % pl->p.n_ei == 0 && pl->present != pl->landed) {
     pl->present = pl->landed;
+    pl->tables_dirty = true;
   }
   return CPRA_OK;
 }
@@ -594,6 +680,76 @@ static cpra_status advance(cpra_plan_t pl, const Ops& ops, int32_t algo, double 
   return step_once(pl, ops, algo, beta);
 }
 
+// Several plans of one size and precision advanced together, one launch per pass per iteration
+// (per kFuseMax plans and per kind of iteration: boundary or not, estimate or not), on the stream
+// of the first plan.  That stream is ordered after every plan's stream first, the plans' own work
+// (table uploads) goes to it meanwhile, and every plan's stream is ordered after it at the end.
+static cpra_status fused_batch(std::vector<cpra_plan_t>& pls, const Ops& ops, int32_t n_iter, int32_t algo,
+                               double beta) {
+  const hipStream_t bs = pls[0]->stream;
+  std::vector<hipStream_t> own(pls.size());
+  for (size_t i = 0; i < pls.size(); ++i) {
+    cpra_plan_t pl = pls[i];
+    own[i] = pl->stream;
+    if (pl->stream != bs) {
+      if (!pl->ev_batch) HIPCHK(pl, hipEventCreateWithFlags(&pl->ev_batch, hipEventDisableTiming));
+      HIPCHK(pl, hipEventRecord(pl->ev_batch, pl->stream));
+      HIPCHK(pl, hipStreamWaitEvent(bs, pl->ev_batch, 0));
+    }
+    pl->stream = bs;
+  }
+  cpra_status st = CPRA_OK;
+  std::vector<cpra_plan_t> grp;
+  for (int32_t it = 0; it < n_iter && st == CPRA_OK; ++it) {
+    for (cpra_plan_t pl : pls) {
+      st = refresh_tables(pl);
+      if (st != CPRA_OK) break;
+    }
+    if (st != CPRA_OK) break;
+    // the kinds of iteration present: (boundary, mode); usually one
+    for (int kind = 0; kind < 4; ++kind) {
+      grp.clear();
+      for (cpra_plan_t pl : pls) {
+        const bool boundary = (pl->k % pl->p.n_ei) == 0;
+        const bool estimate = ((pl->k + 1) % pl->p.n_ei) == 0;
+        if ((boundary ? 1 : 0) + (estimate ? 2 : 0) == kind) grp.push_back(pl);
+      }
+      if (grp.empty()) continue;
+      ops.fused_step(grp.data(), (int)grp.size(), (kind & 1) != 0, (kind & 2) ? 2 : mode_of(algo), beta, bs);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) {
+        st = fail(grp[0], CPRA_ERR_DEVICE, "fused launch: %s", hipGetErrorString(e));
+        break;
+      }
+    }
+    for (cpra_plan_t pl : pls) {
+      if (pl->k % pl->p.n_ei == 0) pl->cur ^= 1;
+      pl->k += 1;
+    }
+  }
+  for (size_t i = 0; i < pls.size(); ++i) {
+    cpra_plan_t pl = pls[i];
+    pl->stream = own[i];
+    if (own[i] != bs) {
+      if (hipEventRecord(pl->ev_batch, bs) != hipSuccess || hipStreamWaitEvent(own[i], pl->ev_batch, 0) != hipSuccess)
+        st = fail(pl, CPRA_ERR_DEVICE, "batch stream ordering");
+    }
+  }
+  return st;
+}
+
+cpra_status cpra_set_batch_fusion(int32_t max_n) {
+  if (max_n < 0) return fail(nullptr, CPRA_ERR_ARG, "max_n must be >= 0");
+  g_fuse_max_n = max_n;
+  return CPRA_OK;
+}
+
+cpra_status cpra_get_batch_fusion(int32_t* max_n) {
+  if (!max_n) return fail(nullptr, CPRA_ERR_ARG, "max_n is NULL");
+  *max_n = g_fuse_max_n;
+  return CPRA_OK;
+}
+
 cpra_status cpra_iterate_batch(cpra_plan_t* plans, int32_t count, int32_t n_iter, int32_t algo, double beta) {
   if (!plans) return fail(nullptr, CPRA_ERR_ARG, "plans is NULL");
   if (count < 0) return fail(nullptr, CPRA_ERR_ARG, "count < 0");
@@ -609,18 +765,48 @@ cpra_status cpra_iterate_batch(cpra_plan_t* plans, int32_t count, int32_t n_iter
     bool any = false;
     for (int n = 0; n < pl->p.Np; ++n) any = any || pl->landed[n];
     if (!any) return fail(pl, CPRA_ERR_STATE, "no angle has been submitted");
+    const cpra_status st = check_data(pl);
+    if (st != CPRA_OK) return st;
   }
-  std::vector<Ops> ops(count);
-  std::vector<int32_t> left(count, n_iter);
-  for (int i = 0; i < count; ++i) ops[i] = ops_of(plans[i]->p);
   cpra_status worst = CPRA_OK;
+  if (n_iter == 0) return worst;
+  // size classes (N, real type, amplitude type) of two or more plans with three-tap coupling and
+  // launch-by-launch episodes go through fused launches; every other plan advances on its own
+  std::vector<std::vector<cpra_plan_t>> classes;
+  std::vector<cpra_plan_t> single;
+  for (int i = 0; i < count; ++i) {
+    cpra_plan_t pl = plans[i];
+    if (pl->p.N > g_fuse_max_n || pl->K > 1 || pl->use_graphs || pl->chunk > 0) {
+      single.push_back(pl);
+      continue;
+    }
+    bool placed = false;
+    for (auto& c : classes)
+      if (c[0]->p.N == pl->p.N && c[0]->p.real_type == pl->p.real_type && c[0]->p.amp_type == pl->p.amp_type) {
+        c.push_back(pl);
+        placed = true;
+        break;
+      }
+    if (!placed) classes.push_back({pl});
+  }
+  for (auto& c : classes) {
+    if (c.size() == 1) {
+      single.push_back(c[0]);
+      continue;
+    }
+    const cpra_status st = fused_batch(c, ops_of(c[0]->p), n_iter, algo, beta);
+    if (st != CPRA_OK) worst = st;
+  }
+  std::vector<Ops> ops(single.size());
+  std::vector<int32_t> left(single.size(), n_iter);
+  for (size_t i = 0; i < single.size(); ++i) ops[i] = ops_of(single[i]->p);
   // round robin: each round advances every plan by its boundary iteration, by the rest of its
   // episode, or by a whole episode when the plan replays captured episodes
-  for (bool more = n_iter > 0; more;) {
+  for (bool more = !single.empty(); more;) {
     more = false;
-    for (int i = 0; i < count; ++i) {
-      if (left[i] <= 0 || plans[i]->poisoned) continue;
-      const cpra_status st = advance(plans[i], ops[i], algo, beta, left[i]);
+    for (size_t i = 0; i < single.size(); ++i) {
+      if (left[i] <= 0 || single[i]->poisoned) continue;
+      const cpra_status st = advance(single[i], ops[i], algo, beta, left[i]);
       if (st != CPRA_OK) worst = st;
       more = more || left[i] > 0;
     }
@@ -634,6 +820,10 @@ cpra_status cpra_iterate(cpra_plan_t pl, int32_t n_iter, int32_t algo, double be
   if (n_iter < 0) return fail(pl, CPRA_ERR_ARG, "n_iter < 0");
   if (algo != CPRA_HIO && algo != CPRA_ER && algo != CPRA_RAAR) return fail(pl, CPRA_ERR_ARG, "bad algo");
   if (!std::isfinite(beta)) return fail(pl, CPRA_ERR_ARG, "beta must be finite");
+  {
+    const cpra_status st = check_data(pl);
+    if (st != CPRA_OK) return st;
+  }
   const int Np = pl->p.Np;
   {
     bool any = false;
@@ -1121,6 +1311,10 @@ cpra_status cpra_read_objects(cpra_plan_t pl, void* out, int32_t ptr_kind) {
   if (pl->poisoned) return fail(pl, CPRA_ERR_STATE, "plan is poisoned by an earlier device error");
   if (!out) return fail(pl, CPRA_ERR_ARG, "out is NULL");
   if (ptr_kind != CPRA_PTR_HOST && ptr_kind != CPRA_PTR_DEVICE) return fail(pl, CPRA_ERR_ARG, "bad ptr_kind");
+  {
+    const cpra_status st = check_data(pl);
+    if (st != CPRA_OK) return st;
+  }
   const size_t bytes = (size_t)pl->R * pl->p.Np * pl->p.N * pl->p.N * (pl->p.real_type == CPRA_REAL_F64 ? 8 : 4);
   const char* src = pl->ws + (pl->cur ? pl->L.g1 : pl->L.g0);
   HIPCHK(pl, hipMemcpyAsync(out, src, bytes, ptr_kind == CPRA_PTR_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
@@ -1135,7 +1329,9 @@ cpra_status cpra_assemble_volume(cpra_plan_t pl, void* d_volume) {
   if (!d_volume) return fail(pl, CPRA_ERR_ARG, "d_volume is NULL");
   if (pl->k == 0 || pl->k % pl->p.n_ei != 0)
     return fail(pl, CPRA_ERR_STATE, "step D needs an episode end (k=%lld, n_ei=%d)", (long long)pl->k, pl->p.n_ei);
-  cpra_status st = ensure_stepd_tables(pl);
+  cpra_status st = check_data(pl);
+  if (st != CPRA_OK) return st;
+  st = ensure_stepd_tables(pl);
   if (st != CPRA_OK) return st;
   Ops ops = ops_of(pl->p);
   ops.assemble(pl, d_volume);

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <unistd.h>
+
 #include <string>
 #include <vector>
 
@@ -16,8 +18,8 @@
 namespace cpra_impl {
 
 struct Layout {
-  size_t P, Pmid, g0, g1, A2, ampscale, maskw, den, tw, coup, alist, errpart, errhist, flags, stage_I,
-      stage_S, csr_ptr, csr_ent, csr_w, cnt_inv, plane, prep_part, mtab, swk, ctab, total;
+  size_t P, Pmid, g0, g1, A2, ampscale, maskw, den, tw, coup, alist, iota, errpart, errhist, flags, stage_I,
+      stage_S, csr_ptr, csr_cell, csr_ent, csr_w, cnt_inv, plane, prep_part, mtab, swk, ctab, total;
   int zc;   // z-planes per step-D chunk
 };
 
@@ -67,7 +69,17 @@ struct cpra_plan_s {
   std::vector<int32_t> csr_rp, csr_ent;
   std::vector<double> csr_wd, inv_d;
   std::vector<float> csr_wf, inv_f;
+  std::vector<cpra::CellRec> cell_h;
   hipStream_t cap_stream = nullptr;
+  hipEvent_t ev_batch = nullptr;   // orders a fused batch's stream and the plan's own stream
+  // pinned staging of the coupling tables and slot list (ev_tab: the last upload has completed)
+  void* h_tab = nullptr;
+  hipEvent_t ev_tab = nullptr;
+  bool tab_pending = false;
+  // the data check of asynchronous submits: the device flag copied to pinned memory (ev_flag)
+  int32_t* h_flag = nullptr;
+  hipEvent_t ev_flag = nullptr;
+  bool flag_pending = false;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int g_algo = -1;
   double g_beta = 0.0;
@@ -78,9 +90,18 @@ struct cpra_plan_s {
       g = nullptr;
     }
   }
+  int pid = 0;                 // creating process: a forked child must make no HIP call on its copy
   ~cpra_plan_s() {
+    if (pid != (int)getpid()) return;
     drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (ev_batch) (void)hipEventDestroy(ev_batch);
+    if (tab_pending) (void)hipEventSynchronize(ev_tab);
+    if (flag_pending) (void)hipEventSynchronize(ev_flag);
+    if (ev_tab) (void)hipEventDestroy(ev_tab);
+    if (ev_flag) (void)hipEventDestroy(ev_flag);
+    if (h_tab) (void)hipHostFree(h_tab);
+    if (h_flag) (void)hipHostFree(h_flag);
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
   }
 };
@@ -119,6 +140,7 @@ struct Ops {
   void (*shrinkwrap)(cpra_plan_t, const int*, int, int, double);
   void (*couple_taps)(cpra_plan_t, const int*, int, int, int);
   void (*refine)(cpra_plan_t, const RefineArgs&);
+  void (*fused_step)(cpra_plan_t const*, int, bool, int, double, hipStream_t);
 };
 
 template <int N, typename T, typename AP>
@@ -288,8 +310,52 @@ struct Impl {
       }
     }
   }
+  // one iteration of `count` plans of this size and precision, one launch per pass for every
+  // kFuseMax plans, on stream st: each plan's listed slots (its alist), all coupled at a boundary
+  // or none, all in row-pass `mode`.  Same arithmetic per slot as `step`.
+  static void fused_step(cpra_plan_t const* pls, int count, bool couple, int mode, double beta, hipStream_t st) {
+    using CG = ColGeom<N>;
+    using RG = RowGeom<N>;
+    for (int b0 = 0; b0 < count; b0 += kFuseMax) {
+      const int bn = count - b0 < kFuseMax ? count - b0 : kFuseMax;
+      FuseTab<T, AP> ft{};
+      ft.count = bn;
+      int tot = 0;
+      for (int i = 0; i < bn; ++i) {
+        cpra_plan_t pl = pls[b0 + i];
+        FusePlan<T, AP>& q = ft.p[i];
+        ft.start[i] = tot;
+        q.P = at<C>(pl, pl->L.P);
+        q.Pmid = at<C>(pl, pl->L.Pmid);
+        q.A2 = at<AP>(pl, pl->L.A2);
+        q.ampscale = at<T>(pl, pl->L.ampscale);
+        q.tw = at<C>(pl, pl->L.tw);
+        q.alist = at<int>(pl, pl->L.alist);
+        q.coup = at<cpra::Coupling>(pl, pl->L.coup);
+        q.gin = at<T>(pl, pl->cur ? pl->L.g1 : pl->L.g0);
+        q.gout = at<T>(pl, (couple ? pl->cur ^ 1 : pl->cur) ? pl->L.g1 : pl->L.g0);
+        q.maskw = at<uint32_t>(pl, pl->L.maskw);
+        q.npd = pl->p.Np;
+        q.positivity = pl->p.positivity;
+        tot += (int)pl->alist_h.size();
+      }
+      ft.start[bn] = tot;
+      if (tot == 0) continue;
+      dim3 gc(CG::TILES, tot), bc(CG::R1 * CG::C);
+      if constexpr (CG::S == 2) {
+        if (couple) k_colpair_fused<N, T, AP, true><<<gc, bc, 0, st>>>(ft);
+        else k_colpair_fused<N, T, AP, false><<<gc, bc, 0, st>>>(ft);
+      } else {
+        if (couple) k_col_fused<N, T, AP, true><<<gc, bc, 0, st>>>(ft);
+        else k_col_fused<N, T, AP, false><<<gc, bc, 0, st>>>(ft);
+      }
+      dim3 gr(N / RG::RPB, tot), br(RG::T * RG::RPB);
+      if (couple) k_row_fused<N, T, AP, true><<<gr, br, 0, st>>>(ft, mode, (T)beta);
+      else k_row_fused<N, T, AP, false><<<gr, br, 0, st>>>(ft, mode, (T)beta);
+    }
+  }
   static void assemble(cpra_plan_t pl, void* vol) {
-    stepd_run<N, T>(at<C>(pl, pl->L.P), at<int>(pl, pl->L.csr_ptr), at<int>(pl, pl->L.csr_ent),
+    stepd_run<N, T>(at<C>(pl, pl->L.P), at<CellRec>(pl, pl->L.csr_cell), at<int>(pl, pl->L.csr_ent),
                     pl->p.insertion == CPRA_INSERT_BILINEAR ? at<T>(pl, pl->L.csr_w) : nullptr,
                     at<T>(pl, pl->L.cnt_inv), at<C>(pl, pl->L.tw), at<C>(pl, pl->L.plane), pl->L.zc,
                     reinterpret_cast<T*>(vol), pl->stream);
@@ -303,7 +369,7 @@ template <int N, typename T, typename AP> Ops ops_for() {
              &Impl<N, T, AP>::step,     &Impl<N, T, AP>::assemble, &Impl<N, T, AP>::reload,
              &Impl<N, T, AP>::colerr,   &Impl<N, T, AP>::moments,  &Impl<N, T, AP>::twin,
              &Impl<N, T, AP>::merge_avg, &Impl<N, T, AP>::shrinkwrap, &Impl<N, T, AP>::couple_taps,
-             &Impl<N, T, AP>::refine};
+             &Impl<N, T, AP>::refine, &Impl<N, T, AP>::fused_step};
 }
 
 

@@ -506,12 +506,12 @@ __device__ __forceinline__ void block_reduce_store(double v, double* out) {
 // MODE 0: iteration (read P, optionally coupled; FFT_z; error; modulus
 // projection; IFFT_z; write Pmid).  MODE 1: initial guess (generate the
 // Hermitian part of (-1)^(w+u) A e^{i phi} / N^2, IFFT_z, write Pmid).
-template <int N, typename T, typename AP, int MODE, bool ERR, bool CPL = false>
-__global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
-    k_col(const cx<T>* __restrict__ P, cx<T>* __restrict__ Pmid, const AP* __restrict__ A2,
-          const T* __restrict__ ampscale, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
-          const Coupling* __restrict__ coup, int npd, double* __restrict__ errpart, int ntiles,
-          uint64_t seed) {
+// The body runs slot n's tile blockIdx.x; errout receives the tile's FP64 error partial (ERR).
+template <int N, typename T, typename AP, int MODE, bool ERR, bool CPL>
+__device__ __forceinline__ void col_body(const cx<T>* __restrict__ P, cx<T>* __restrict__ Pmid,
+                                         const AP* __restrict__ A2, const T* __restrict__ ampscale,
+                                         const cx<T>* __restrict__ tw, int n, const Coupling* __restrict__ coup,
+                                         int npd, double* __restrict__ errout, uint64_t seed) {
   using Gm = ColGeom<N>;
   using TL = TwLayout<N>;
   using C = cx<T>;
@@ -522,8 +522,6 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
   const int col = threadIdx.x % CC;
   const int a = threadIdx.x / CC;
   const int tile = blockIdx.x;
-  const int ai = blockIdx.y;
-  const int n = alist[ai];
   static_assert(PixCfg<N>::CB == CC, "one chunk per tile");
   const int j0 = tile * CC;
   const int j = j0 + col;
@@ -710,8 +708,19 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
     });
   }
   if constexpr (MODE == 0 && ERR) {
-    block_reduce_store<N, T>(err, errpart + (size_t)ai * ntiles + tile);
+    block_reduce_store<N, T>(err, errout);
   }
+}
+
+template <int N, typename T, typename AP, int MODE, bool ERR, bool CPL = false>
+__global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
+    k_col(const cx<T>* __restrict__ P, cx<T>* __restrict__ Pmid, const AP* __restrict__ A2,
+          const T* __restrict__ ampscale, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
+          const Coupling* __restrict__ coup, int npd, double* __restrict__ errpart, int ntiles,
+          uint64_t seed) {
+  const int ai = blockIdx.y;
+  col_body<N, T, AP, MODE, ERR, CPL>(P, Pmid, A2, ampscale, tw, alist[ai], coup, npd,
+                                     ERR ? errpart + (size_t)ai * ntiles + blockIdx.x : nullptr, seed);
 }
 
 // Column pass with paired step-2 DFTs (S = 2): R1 = 2 R2 threads per column,
@@ -726,12 +735,12 @@ __device__ __forceinline__ cx<T> pair_lane(cx<T> v) {
   return mk<cx<T>>(__shfl_xor(v.x, PM), __shfl_xor(v.y, PM));
 }
 
-template <int N, typename T, typename AP, int MODE, bool ERR, bool CPL = false>
-__global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((amdgpu_waves_per_eu(4)))
-    k_col_pair(const cx<T>* __restrict__ P, cx<T>* __restrict__ Pmid, const AP* __restrict__ A2,
-               const T* __restrict__ ampscale, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
-               const Coupling* __restrict__ coup, int npd, double* __restrict__ errpart, int ntiles,
-               uint64_t seed) {
+template <int N, typename T, typename AP, int MODE, bool ERR, bool CPL>
+__device__ __forceinline__ void col_pair_body(const cx<T>* __restrict__ P, cx<T>* __restrict__ Pmid,
+                                              const AP* __restrict__ A2, const T* __restrict__ ampscale,
+                                              const cx<T>* __restrict__ tw, int n,
+                                              const Coupling* __restrict__ coup, int npd,
+                                              double* __restrict__ errout, uint64_t seed) {
   using Gm = ColGeom<N>;
   using TL = TwLayout<N>;
   using C = cx<T>;
@@ -748,8 +757,6 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
   const int sh = a & 1;
   const int c = a >> 1;                    // step 2: owned c and half sh
   const int tile = blockIdx.x;
-  const int ai = blockIdx.y;
-  const int n = alist[ai];
   const int j0 = col_tile_start<N>(tile);
   const int j = j0 + col;
   const size_t plane = (size_t)N * H;
@@ -926,8 +933,19 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((am
     });
   }
   if constexpr (MODE == 0 && ERR) {
-    block_reduce_store<N, T, NT>(err, errpart + (size_t)ai * ntiles + tile);
+    block_reduce_store<N, T, NT>(err, errout);
   }
+}
+
+template <int N, typename T, typename AP, int MODE, bool ERR, bool CPL = false>
+__global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((amdgpu_waves_per_eu(4)))
+    k_col_pair(const cx<T>* __restrict__ P, cx<T>* __restrict__ Pmid, const AP* __restrict__ A2,
+               const T* __restrict__ ampscale, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
+               const Coupling* __restrict__ coup, int npd, double* __restrict__ errpart, int ntiles,
+               uint64_t seed) {
+  const int ai = blockIdx.y;
+  col_pair_body<N, T, AP, MODE, ERR, CPL>(P, Pmid, A2, ampscale, tw, alist[ai], coup, npd,
+                                          ERR ? errpart + (size_t)ai * ntiles + blockIdx.x : nullptr, seed);
 }
 
 // ---------------------------------------------------------------- row pass
@@ -970,11 +988,11 @@ __device__ __forceinline__ C partner_c(C v, int partner_lane_idx) {
 // exchange, F1-point IDFT) -> g' in the space layout; real-space update with
 // the support bits and g; R2C back (F1-point DFT, twiddle, LDS exchange,
 // F2-point DFT, post-processing) -> P.
-template <int N, typename T, bool CPL = false>
-__global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((amdgpu_waves_per_eu(4)))
-    k_row(const cx<T>* __restrict__ Pmid, cx<T>* __restrict__ P, const T* gin, T* gout,
-          const uint32_t* __restrict__ maskw, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
-          const Coupling* __restrict__ coup, int npd, int mode, T beta, int positivity) {
+template <int N, typename T, bool CPL>
+__device__ __forceinline__ void row_body(const cx<T>* __restrict__ Pmid, cx<T>* __restrict__ P, const T* gin,
+                                         T* gout, const uint32_t* __restrict__ maskw,
+                                         const cx<T>* __restrict__ tw, int n, const Coupling* __restrict__ coup,
+                                         int npd, int mode, T beta, int positivity) {
   using Gm = RowGeom<N>;
   using TL = TwLayout<N>;
   using C = cx<T>;
@@ -984,7 +1002,6 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
   __shared__ C lds[RPB * Gm::RSTRIDE];
   const int tau = threadIdx.x % TT;       // owned frequency class k1 = tau
   const int r = threadIdx.x / TT;
-  const int n = alist[blockIdx.y];
   const int z = blockIdx.x * RPB + r;
   C* L0 = lds + r * Gm::RSTRIDE;
   const size_t pbase = (size_t)n * N * H;           // the angle's complex planes
@@ -1169,6 +1186,75 @@ __global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((
       });
     });
   }
+}
+
+template <int N, typename T, bool CPL = false>
+__global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((amdgpu_waves_per_eu(4)))
+    k_row(const cx<T>* __restrict__ Pmid, cx<T>* __restrict__ P, const T* gin, T* gout,
+          const uint32_t* __restrict__ maskw, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
+          const Coupling* __restrict__ coup, int npd, int mode, T beta, int positivity) {
+  row_body<N, T, CPL>(Pmid, P, gin, gout, maskw, tw, alist[blockIdx.y], coup, npd, mode, beta, positivity);
+}
+
+// ---------------------------------------------------------------- fused launches
+// One launch of a pass over the listed slots of up to kFuseMax plans of the same N and precision
+// (several scans iterated together): work item i (blockIdx.y) belongs to plan p with
+// start[p] <= i < start[p + 1] and is that plan's slot alist[i - start[p]].  Every plan brings its
+// own planes, data, coupling table and current iterate buffers; the arithmetic per slot is that
+// of the single-plan launch.
+constexpr int kFuseMax = 16;
+template <typename T, typename AP> struct FusePlan {
+  cx<T>* P;
+  cx<T>* Pmid;
+  const AP* A2;
+  const T* ampscale;
+  const cx<T>* tw;
+  const int* alist;
+  const Coupling* coup;
+  const T* gin;
+  T* gout;
+  const uint32_t* maskw;
+  int npd, positivity;
+};
+template <typename T, typename AP> struct FuseTab {
+  int count;
+  int start[kFuseMax + 1];
+  FusePlan<T, AP> p[kFuseMax];
+};
+
+__device__ __forceinline__ int fuse_plan_of(const int* start, int count, int i) {
+  int p = 0;
+  for (int q = 1; q < count; ++q) p = i >= start[q] ? q : p;
+  return p;
+}
+
+template <int N, typename T, typename AP, bool CPL>
+__global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) __attribute__((amdgpu_waves_per_eu(4)))
+    k_colpair_fused(const FuseTab<T, AP> ft) {
+  const int i = blockIdx.y;
+  const int p = fuse_plan_of(ft.start, ft.count, i);
+  const FusePlan<T, AP>& q = ft.p[p];
+  col_pair_body<N, T, AP, 0, false, CPL>(q.P, q.Pmid, q.A2, q.ampscale, q.tw, q.alist[i - ft.start[p]], q.coup,
+                                         q.npd, nullptr, 0);
+}
+
+template <int N, typename T, typename AP, bool CPL>
+__global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) k_col_fused(const FuseTab<T, AP> ft) {
+  const int i = blockIdx.y;
+  const int p = fuse_plan_of(ft.start, ft.count, i);
+  const FusePlan<T, AP>& q = ft.p[p];
+  col_body<N, T, AP, 0, false, CPL>(q.P, q.Pmid, q.A2, q.ampscale, q.tw, q.alist[i - ft.start[p]], q.coup, q.npd,
+                                    nullptr, 0);
+}
+
+template <int N, typename T, typename AP, bool CPL>
+__global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((amdgpu_waves_per_eu(4)))
+    k_row_fused(const FuseTab<T, AP> ft, int mode, T beta) {
+  const int i = blockIdx.y;
+  const int p = fuse_plan_of(ft.start, ft.count, i);
+  const FusePlan<T, AP>& q = ft.p[p];
+  row_body<N, T, CPL>(q.Pmid, q.P, q.gin, q.gout, q.maskw, q.tw, q.alist[i - ft.start[p]],
+                      q.coup, q.npd, mode, beta, q.positivity);
 }
 
 // ---------------------------------------------------------------- error reduce

@@ -43,11 +43,18 @@ __device__ __forceinline__ cx<T> spectrum_at(const cx<T>* Pn, int z, int u) {
   return conj(Pn[pix<N>(z, N - u)]);
 }
 
+// Per cell (ky, kx) of the insertion grid, one 16-byte record: the first entry's code n N + u (or
+// -1 for an empty cell), the CSR range [begin, end) of all its entries, and the inverse count (or
+// inverse weight sum) as FP32 bits.  One load gives what a cell with a single entry needs.
+struct CellRec {
+  int first, begin, end, inv_bits;
+};
+
 // Rows: gather Q_z[ky][:] and inverse transform along kx.
 // Block: RB rows x R1 threads; grid: (N / RB) * nz (see the mapping below).
 template <int N, typename T, int RB>
 __global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
-    k_stepd_rows(const cx<T>* __restrict__ P, const int* __restrict__ ptr, const int* __restrict__ ent,
+    k_stepd_rows(const cx<T>* __restrict__ P, const CellRec* __restrict__ cells, const int* __restrict__ ent,
                  const T* __restrict__ wts, const T* __restrict__ cnt_inv, const cx<T>* __restrict__ tw,
                  cx<T>* __restrict__ plane, int z0, int nz) {
   using C = cx<T>;
@@ -82,33 +89,28 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
     if (wts) s = cscale(s, wts[e]);      // bilinear insertion weight
     return s;
   };
-  // the cells go in groups of G, each gathered in three batches (entry ranges, first entries,
-  // the rest) so that the dependent loads of different cells overlap; per cell the entries are
-  // still summed in CSR order
+  // the cells go in groups of G, each gathered in two dependent batches (the cell records, then
+  // the first entries' samples) so that the loads of different cells overlap; the further entries
+  // of the cells that have them follow in CSR order
   constexpr int G = R2 < 8 ? R2 : 8;
 #pragma unroll
   for (int g0 = 0; g0 < R2; g0 += G) {
-    int e0[G], e1[G], code[G];
+    CellRec rec[G];
 #pragma unroll
-    for (int i = 0; i < G; ++i) {
-      const int cell = ky * N + a + R1 * (g0 + i);
-      e0[i] = ptr[cell];
-      e1[i] = ptr[cell + 1];
-    }
-#pragma unroll
-    for (int i = 0; i < G; ++i) code[i] = e0[i] < e1[i] ? ent[e0[i]] : -1;
-#pragma unroll
-    for (int i = 0; i < G; ++i) v[g0 + i] = code[i] >= 0 ? sample(e0[i], code[i]) : mk<C>((T)0, (T)0);
+    for (int i = 0; i < G; ++i) rec[i] = cells[ky * N + a + R1 * (g0 + i)];
 #pragma unroll
     for (int i = 0; i < G; ++i)
-      for (int e = e0[i] + 1; e < e1[i]; ++e) v[g0 + i] = cadd(v[g0 + i], sample(e, ent[e]));
-  }
+      v[g0 + i] = rec[i].first >= 0 ? sample(rec[i].begin, rec[i].first) : mk<C>((T)0, (T)0);
 #pragma unroll
-  for (int b = 0; b < R2; ++b) {
-    const int kx = a + R1 * b;
-    T f = cnt_inv[ky * N + kx];
-    if ((ky + kx) & 1) f = -f;
-    v[b] = cscale(v[b], f);
+    for (int i = 0; i < G; ++i) {
+      for (int e = rec[i].begin + 1; e < rec[i].end; ++e) v[g0 + i] = cadd(v[g0 + i], sample(e, ent[e]));
+      const int kx = a + R1 * (g0 + i);
+      T f;
+      if constexpr (std::is_same<T, float>::value) f = __int_as_float(rec[i].inv_bits);
+      else f = cnt_inv[ky * N + kx];
+      if ((ky + kx) & 1) f = -f;
+      v[g0 + i] = cscale(v[g0 + i], f);
+    }
   }
   // inverse four-step along kx = a + R1 b -> x = c + R2 d
   dft<R2, +1>(v);
@@ -166,15 +168,15 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* CC)
 
 // tw: W_N^j, j < N (the first N entries of the plan's twiddle table)
 template <int N, typename T>
-void stepd_run(const cx<T>* P, const int* ptr, const int* ent, const T* wts, const T* cnt_inv, const cx<T>* tw,
-               cx<T>* plane, int zc, T* vol, hipStream_t st) {
+void stepd_run(const cx<T>* P, const CellRec* cells, const int* ent, const T* wts, const T* cnt_inv,
+               const cx<T>* tw, cx<T>* plane, int zc, T* vol, hipStream_t st) {
   constexpr int R1 = StepdCfg<N>::R1, R2 = StepdCfg<N>::R2;
   // rows / columns per workgroup: up to 256 threads, LDS within 128 KiB
   constexpr int RB = stepd_lines<N, T>(256 / R1 < N ? 256 / R1 : N, (size_t)R2 * (R1 + 1));
   constexpr int CC = stepd_lines<N, T>(256 / R1 < N ? 256 / R1 : N, (size_t)R2 * R1);
   for (int z0 = 0; z0 < N; z0 += zc) {
     const int nz = (N - z0) < zc ? (N - z0) : zc;
-    k_stepd_rows<N, T, RB><<<(N / RB) * nz, R1 * RB, 0, st>>>(P, ptr, ent, wts, cnt_inv, tw, plane, z0, nz);
+    k_stepd_rows<N, T, RB><<<(N / RB) * nz, R1 * RB, 0, st>>>(P, cells, ent, wts, cnt_inv, tw, plane, z0, nz);
     k_stepd_cols<N, T, CC><<<dim3(N / CC, nz), R1 * CC, 0, st>>>(plane, tw, vol, z0);
   }
 }

@@ -12,7 +12,8 @@ other scans in the mix: frame j (in landing order) is submitted only after the s
 exactly j * r_frame iterations; each landed frame adds r_frame iterations of credit and the last
 one adds r_final more.  r_frame and r_final are multiples of n_ei, so every chunk of work is whole
 episodes.  All scans with credit advance together, one episode per round, through
-cpra_iterate_batch (each plan on its own stream, so their kernels overlap on the device); at most
+cpra_iterate_batch (scans of one size share launches, size classes overlap on their streams); frames
+are submitted without waiting for the GPU (the data check completes in stream order); at most
 `depth` episodes per scan are in flight, which bounds how long a frame submission can wait; a
 scan whose last frame has landed may queue up to `depth_final` and is issued first.
 """
@@ -136,7 +137,7 @@ class Server:
             if s.credit == 0 and s.arrived and s.n_submitted < s.n_expected:
                 n, I, S, _ = s.arrived.popleft()
                 with self.stream_ctx(s.plan):
-                    s.plan.submit(n, I, S)
+                    s.plan.submit(n, I, S, asynchronous=True)
                 s.n_submitted += 1
                 s.credit += self.r_frame + (self.r_final if s.n_submitted == s.n_expected else 0)
                 progressed = True

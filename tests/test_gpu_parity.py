@@ -600,6 +600,93 @@ def test_iterate_batch_matches_alone(torch):
     assert [p.k for p in plans] == [k for k, _ in alone]
 
 
+@pytest.mark.parametrize("real", [F32, F64])
+def test_fused_batch_matches_alone(torch, real):
+    """cpra_iterate_batch with shared launches: five scans of N = 128 (different N_p, episode
+    phases, streams and partial angle sets; one lands more angles between the batch calls) and two
+    of N = 64 advance together, one column-pass and one row-pass launch per size class and kind
+    of iteration; every scan ends bit-identical to the same scan iterated alone, with and without
+    the shared launches."""
+    import paper_2402_05283_amd as cp
+    specs = [(128, 6, 1), (128, 9, 3), (128, 4, 0), (128, 7, 4), (128, 5, 2), (64, 8, 1), (64, 5, 0)]
+    scans = {(N, Np): make_scan(1, N=N, Np=Np) for N, Np, _ in specs}
+
+    def make(N, Np, k0, stream, i):
+        sc = scans[(N, Np)]
+        p = cp.Plan(N, Np, theta=sc["theta"], n_ei=5, seed=sc["phase_seed"] + i, stream=stream, real=real)
+        land = Np - 2 if i % 2 else Np                      # odd scans start with a partial angle set
+        p.submit(0, torch.from_numpy(sc["I"][:land]).cuda(), torch.from_numpy(sc["support"][:land]).cuda())
+        if k0:
+            p.iterate(k0, cp.HIO, 0.9)
+        return p
+
+    def finish(p, N, Np, i):
+        if i % 2:
+            sc = scans[(N, Np)]
+            p.submit(Np - 2, torch.from_numpy(sc["I"][Np - 2:]).cuda(), torch.from_numpy(sc["support"][Np - 2:]).cuda())
+
+    banner(f"fused batch alone real={real}")
+    alone = []
+    for i, (N, Np, k0) in enumerate(specs):
+        p = make(N, Np, k0, None, i)
+        p.iterate(7, cp.HIO, 0.9)
+        finish(p, N, Np, i)
+        p.iterate(9, cp.HIO, 0.9)
+        p.iterate(4, cp.ER, 0.0)
+        torch.cuda.synchronize()
+        alone.append((p.k, p.objects().cpu().numpy()))
+    for fuse in (1024, 0):
+        banner(f"fused batch real={real} fusion up to N={fuse}")
+        prev = cp.set_batch_fusion(fuse)
+        try:
+            streams = [torch.cuda.Stream() for _ in specs]
+            plans = [make(N, Np, k0, s, i) for i, ((N, Np, k0), s) in enumerate(zip(specs, streams))]
+            cp.iterate_batch(plans, 7, cp.HIO, 0.9)
+            for i, ((N, Np, _), p) in enumerate(zip(specs, plans)):
+                finish(p, N, Np, i)
+            cp.iterate_batch(plans, 9, cp.HIO, 0.9)
+            cp.iterate_batch(plans, 4, cp.ER, 0.0)
+            torch.cuda.synchronize()
+        finally:
+            cp.set_batch_fusion(prev)
+        for p, (k, ref) in zip(plans, alone):
+            assert p.k == k
+            assert np.array_equal(p.objects().cpu().numpy(), ref)
+
+
+def test_async_submit(torch):
+    """Submits that do not wait for the GPU (CPRA_PTR_DEVICE_ASYNC): frames landing one by one
+    between iterations give the same objects, bit for bit, as synchronous submits; a NaN in an
+    asynchronous frame is reported by a later call, which poisons the plan."""
+    import paper_2402_05283_amd as cp
+    scan = make_scan(1, Np=8)
+    I = torch.from_numpy(scan["I"]).cuda()
+    S = torch.from_numpy(scan["support"]).cuda()
+    banner("async submit")
+    res = []
+    for asy in (False, True):
+        p = cp.Plan(64, 8, theta=scan["theta"], n_ei=5, seed=scan["phase_seed"])
+        p.submit(0, I[:2], S[:2], asynchronous=asy)
+        for n in range(2, 8):
+            p.iterate(5, cp.HIO, 0.9)
+            p.submit(n, I[n:n + 1], S[n:n + 1], asynchronous=asy)
+        p.iterate(10, cp.HIO, 0.9)
+        torch.cuda.synchronize()
+        res.append(p.objects().cpu().numpy())
+    assert np.array_equal(res[0], res[1])
+    p = cp.Plan(64, 8, theta=scan["theta"], n_ei=5, seed=scan["phase_seed"])
+    bad = I[:4].clone()
+    bad[2, 5, 7] = float("inf")
+    p.submit(0, bad, S[:4], asynchronous=True)
+    torch.cuda.synchronize()
+    with pytest.raises(cp.CpraError) as e:
+        p.iterate(1)
+    assert e.value.status == -6
+    with pytest.raises(cp.CpraError) as e:
+        p.iterate(1)
+    assert e.value.status == -4                    # poisoned
+
+
 def test_api_errors(torch):
     import paper_2402_05283_amd as cp
     scan = make_scan(1, Np=4)

@@ -25,7 +25,7 @@ class FakePlan:
         self.scan, self.log, self.k = scan, log, 0
         self.stream = None
 
-    def submit(self, n, I, S):
+    def submit(self, n, I, S, asynchronous=False):
         self.log.append((self.scan.sid, "submit", n, self.k))
 
     def iterate(self, n):
