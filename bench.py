@@ -722,6 +722,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--amp16", action="store_true", help="FP16 amplitude storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the headline plans with the library's default launch choices")
     ap.add_argument("--iters", type=int, default=ITERS)
     ap.add_argument("--serve-scans", type=int, default=8, help="detector lanes of the serving leg (0: skip)")
     ap.add_argument("--serve-per-lane", type=int, default=13,
@@ -784,6 +786,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    tuning = None
+    if not args.no_autotune:
+        print("[bench] autotuning the launch choices of the N=512 Np=360 shape", file=sys.stderr, flush=True)
+        tuning = cp.autotune(N, NP, n_iter=20, n_ei=N_EI, stream=stream)
+        print(f"[bench] tuning: {tuning}", file=sys.stderr, flush=True)
+
     col_ms = row_ms = 0.0
     col_n = row_n = 0
     lat = []
@@ -800,6 +808,9 @@ def main():
         t0 = time.perf_counter()
         plan = cp.Plan(N, NP, n_ei=N_EI, amp=amp, seed=scan["phase_seed"], stream=stream)
         if timed:
+            if tuning and tuning["graphs"]:
+                # per-pass event timing needs launch-by-launch episodes
+                plan.set_tuning(tuning["row_tile"], tuning["chunk"], 0)
             plan.set_kernel_timing(True)
         plan.submit(0, I, S)
         plan.iterate(args.iters, cp.HIO, BETA)
@@ -868,6 +879,7 @@ def main():
         "iteration_only": {"ms_per_iteration": round(iter_ms, 4),
                            "pattern_iterations_per_s": round(NP / (iter_ms * 1e-3), 1)},
         "roofline": roofline,
+        "tuning": tuning,
     }
     if not args.amp16 and args.iters == ITERS:
         print("[bench] FP16 amplitudes, error history", file=sys.stderr, flush=True)

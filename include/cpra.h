@@ -253,6 +253,37 @@ cpra_status cpra_set_batch_fusion(int32_t max_n);
 cpra_status cpra_get_batch_fusion(int32_t* max_n);
 
 /*
+ * Launch choices of a plan that do not change its results, only its speed:
+ * row_tile 0 runs the row pass with its compiled rows per workgroup, 1 with
+ * twice as many; chunk as cpra_set_chunk; graphs as cpra_set_graphs.
+ * ms_per_iteration: the time one iteration took with them (filled by
+ * cpra_autotune; ignored by cpra_set_tuning).
+ */
+typedef struct {
+  int32_t row_tile;
+  int32_t chunk;
+  int32_t graphs;
+  double ms_per_iteration;
+} cpra_tuning;
+
+/* Apply launch choices to a plan (host only).  ERR_ARG for a bad value. */
+cpra_status cpra_set_tuning(cpra_plan_t plan, const cpra_tuning* t);
+
+/*
+ * Autotuner: build a temporary plan with these parameters on `workspace`
+ * (cpra_workspace_size bytes, the caller's; its contents are overwritten),
+ * fill it with a synthetic scan generated on the device, and time n_iter
+ * HIO iterations (rounded up to whole episodes) for every combination of
+ * row_tile {0, 1}, chunk {0, slots/2, slots/4 where >= 16 slots} and graphs
+ * {0, 1}, each after one warm episode, with HIP events on `hip_stream`.
+ * Returns the fastest in *best and records it for the shape (N, Np, real
+ * type, amplitude type, guesses): plans of that shape created afterwards in
+ * this process start with these choices.  Synchronises the stream.
+ */
+cpra_status cpra_autotune(const cpra_params* params, void* workspace, size_t workspace_bytes, void* hip_stream,
+                          int32_t n_iter, cpra_tuning* best);
+
+/*
  * Shrinkwrap support update (the conventional 2D shrinkwrap step, run by
  * the paper at the end of each episode to tighten the space constraints):
  * for every present angle, blur the current object with the periodic 2D

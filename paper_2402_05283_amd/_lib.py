@@ -31,7 +31,8 @@ EXPORTED = [
     "cpra_coupling_table", "cpra_set_kernel_timing", "cpra_kernel_timing", "cpra_load_objects",
     "cpra_iterate_batch", "cpra_prereconstruct", "cpra_sweep", "cpra_merge", "cpra_shrinkwrap",
     "cpra_read_support", "cpra_refine_workspace_size", "cpra_refine_volume", "cpra_set_graphs", "cpra_set_chunk",
-    "cpra_refine_volume_noalloc", "cpra_set_batch_fusion", "cpra_get_batch_fusion",
+    "cpra_refine_volume_noalloc", "cpra_set_batch_fusion", "cpra_get_batch_fusion", "cpra_set_tuning",
+    "cpra_autotune",
 ]
 
 
@@ -53,6 +54,15 @@ class Params(ctypes.Structure):
         ("taps", ctypes.POINTER(ctypes.c_double)),
         ("n_taps", ctypes.c_int32),
     ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("row_tile", ctypes.c_int32), ("chunk", ctypes.c_int32), ("graphs", ctypes.c_int32),
+                ("ms_per_iteration", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"row_tile": self.row_tile, "chunk": self.chunk, "graphs": self.graphs,
+                "ms_per_iteration": self.ms_per_iteration}
 
 
 class CpraError(RuntimeError):
@@ -96,6 +106,8 @@ def load():
     lib.cpra_refine_volume_noalloc.argtypes = [c.c_void_p, c.c_int32, c.c_int32, c.c_double, c.c_double,
                                                c.c_void_p]
     lib.cpra_set_batch_fusion.argtypes = [c.c_int32]
+    lib.cpra_set_tuning.argtypes = [c.c_void_p, P(Tuning)]
+    lib.cpra_autotune.argtypes = [P(Params), c.c_void_p, c.c_size_t, c.c_void_p, c.c_int32, P(Tuning)]
     lib.cpra_get_batch_fusion.argtypes = [P(c.c_int32)]
     lib.cpra_last_error.argtypes = [c.c_void_p]
     lib.cpra_last_error.restype = c.c_char_p
@@ -116,6 +128,22 @@ def _check(st, plan=None):
     if st != CPRA_OK:
         msg = load().cpra_last_error(plan)
         raise CpraError(st, msg.decode() if msg else "")
+
+
+def autotune(N, Np, n_iter=20, stream=None, **kw):
+    """cpra_autotune on a temporary workspace: the fastest launch choices for plans of this shape
+    (recorded in the library for plans created afterwards); returns them as a dict."""
+    import torch
+    p = make_params(N, Np, **kw)
+    nbytes = workspace_size(p)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    ptr = (ws.data_ptr() + 255) // 256 * 256
+    st = torch.cuda.current_stream() if stream is None else stream
+    best = Tuning()
+    _check(load().cpra_autotune(ctypes.byref(p), ctypes.c_void_p(ptr), nbytes, ctypes.c_void_p(st.cuda_stream),
+                                int(n_iter), ctypes.byref(best)))
+    del ws
+    return best.as_dict()
 
 
 def get_batch_fusion():
@@ -371,6 +399,10 @@ class Plan:
         _check(load().cpra_assemble_volume(self.handle, ctypes.c_void_p(out.data_ptr())), self.handle)
         self._leave(out)
         return out
+
+    def set_tuning(self, row_tile=0, chunk=0, graphs=0):
+        t = Tuning(int(row_tile), int(chunk), int(graphs), 0.0)
+        _check(load().cpra_set_tuning(self.handle, ctypes.byref(t)), self.handle)
 
     def set_graphs(self, enable=True):
         """Replay whole episodes from captured HIP graphs (see cpra_set_graphs)."""

@@ -48,6 +48,16 @@ thread_local std::string g_create_error;
 // interleaved over their streams measured faster than shared launches)
 int g_fuse_max_n = 0;
 
+// autotuned choices per shape (N, Np, real type, amplitude type, guesses), applied to new plans
+struct TuneKey {
+  int N, Np, real, amp, R;
+  bool operator==(const TuneKey& o) const {
+    return N == o.N && Np == o.Np && real == o.real && amp == o.amp && R == o.R;
+  }
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, cpra_tuning>> g_tune;
+
 
 bool size_supported(int N) {
   return N == 64 || N == 128 || N == 192 || N == 256 || N == 384 || N == 512 || N == 1024;
@@ -184,6 +194,7 @@ Layout layout_of(const cpra_params* p) {
   L.mtab = take(S * 3 * 8 + S * 4 * 4 + (S / Np) * 64 + 256);   // step C tables
   L.swk = take((N + 1) * rs);                                      // shrinkwrap window taps
   L.ctab = take(p->n_taps > 3 ? S * p->n_taps * sizeof(cpra::Tap) : 0);   // Eq. 4, 2K+1 taps
+  L.Pc = take(p->n_taps > 3 ? S * N * H * cs : 0);                         // their coupled spectra
   L.total = o;
   return L;
 }
@@ -394,6 +405,17 @@ cpra_status cpra_plan(const cpra_params* params, void* workspace, size_t workspa
     delete pl;
     return CPRA_ERR_DEVICE;
   }
+  {
+    // a shape tuned in this process starts with the tuned choices
+    const TuneKey key{params->N, params->Np, params->real_type, params->amp_type, pl->R};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : g_tune)
+      if (kv.first == key) {
+        pl->row_alt = kv.second.row_tile != 0;
+        pl->chunk = kv.second.chunk;
+        pl->use_graphs = kv.second.graphs != 0;
+      }
+  }
   *out = pl;
   return CPRA_OK;
 }
@@ -549,13 +571,14 @@ cpra_status cpra_submit_angles(cpra_plan_t pl, int32_t first, int32_t count, con
 }
 
 // one iteration of the listed slots; a boundary couples (Eq. 4) on the way in: fused into the
-// passes for three taps, or as a pass of its own into the Pmid scratch for 2K+1 > 3 taps
+// passes for three taps, or as a pass of its own into the Pc planes for 2K+1 > 3 taps (so the
+// column pass reads them and writes Pmid, two distinct planes)
 static void do_step(cpra_plan_t pl, const Ops& ops, const int* al, int nact, bool boundary, bool inplace,
                     int mode, double beta, double* ep) {
   if (boundary && pl->K > 1) {
     const int gout = inplace ? pl->cur : (pl->cur ^ 1);
     ops.couple_taps(pl, al, nact, pl->cur, gout);
-    ops.step(pl, al, nact, false, false, mode, beta, ep, pl->ws + pl->L.Pmid, gout);
+    ops.step(pl, al, nact, false, false, mode, beta, ep, pl->ws + pl->L.Pc, gout);
   } else {
     ops.step(pl, al, nact, boundary, inplace, mode, beta, ep, nullptr, -1);
   }
@@ -678,6 +701,97 @@ static cpra_status advance(cpra_plan_t pl, const Ops& ops, int32_t algo, double 
   }
   n -= 1;
   return step_once(pl, ops, algo, beta);
+}
+
+cpra_status cpra_set_tuning(cpra_plan_t pl, const cpra_tuning* t) {
+  if (!pl) return fail(nullptr, CPRA_ERR_ARG, "plan is NULL");
+  if (!t) return fail(pl, CPRA_ERR_ARG, "tuning is NULL");
+  if (t->row_tile != 0 && t->row_tile != 1) return fail(pl, CPRA_ERR_ARG, "row_tile must be 0 or 1");
+  if (t->chunk < 0) return fail(pl, CPRA_ERR_ARG, "chunk must be >= 0");
+  pl->row_alt = t->row_tile != 0;
+  pl->chunk = t->chunk;
+  pl->use_graphs = t->graphs != 0;
+  pl->drop_graphs();   // captured episodes hold the previous launch shapes
+  return CPRA_OK;
+}
+
+cpra_status cpra_autotune(const cpra_params* params, void* workspace, size_t workspace_bytes, void* hip_stream,
+                          int32_t n_iter, cpra_tuning* best) {
+  if (!best) return fail(nullptr, CPRA_ERR_ARG, "best is NULL");
+  if (n_iter < 1) return fail(nullptr, CPRA_ERR_ARG, "n_iter must be >= 1");
+  cpra_plan_t pl = nullptr;
+  cpra_status st = cpra_plan(params, workspace, workspace_bytes, hip_stream, &pl);
+  if (st != CPRA_OK) return st;
+  struct Guard {
+    cpra_plan_t p;
+    ~Guard() { delete p; }
+  } guard{pl};
+  pl->row_alt = false;
+  pl->chunk = 0;
+  pl->use_graphs = false;
+  // a synthetic scan, staged through the plan's own buffers a few angles at a time
+  const int Np = pl->p.Np;
+  Ops ops = ops_of(pl->p);
+  for (int c0 = 0; c0 < Np; c0 += kStageAngles) {
+    const int cn = std::min(kStageAngles, Np - c0);
+    ops.synth(pl, c0, cn, 0x5eedULL);
+    LAUNCHCHK(pl);
+    st = cpra_submit_angles(pl, c0, cn, at<float>(pl, pl->L.stage_I), at<uint8_t>(pl, pl->L.stage_S),
+                            CPRA_PTR_DEVICE);
+    if (st != CPRA_OK) return st;
+  }
+  // whole episodes, so that every candidate (graphs included) runs the same iterations
+  const int ne = pl->p.n_ei;
+  const int iters = (n_iter + ne - 1) / ne * ne;
+  st = cpra_iterate(pl, ne, CPRA_HIO, 0.9, nullptr);
+  if (st != CPRA_OK) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(pl, hipEventCreate(&e0));
+  HIPCHK(pl, hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evg{e0, e1};
+  const int S = (int)((size_t)Np * pl->R);
+  std::vector<int> chunks = {0};
+  for (int d : {2, 4})
+    if (S / d >= 16) chunks.push_back((S + d - 1) / d);
+  cpra_tuning top{};
+  top.ms_per_iteration = -1.0;
+  for (int rt = 0; rt < 2; ++rt)
+    for (int ch : chunks)
+      for (int gr = 0; gr < 2; ++gr) {
+        const cpra_tuning cand{rt, ch, gr, 0.0};
+        st = cpra_set_tuning(pl, &cand);
+        if (st != CPRA_OK) return st;
+        st = cpra_iterate(pl, ne, CPRA_HIO, 0.9, nullptr);   // warm (and capture a graph)
+        if (st != CPRA_OK) return st;
+        HIPCHK(pl, hipEventRecord(e0, pl->stream));
+        st = cpra_iterate(pl, iters, CPRA_HIO, 0.9, nullptr);
+        if (st != CPRA_OK) return st;
+        HIPCHK(pl, hipEventRecord(e1, pl->stream));
+        HIPCHK(pl, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(pl, hipEventElapsedTime(&ms, e0, e1));
+        const double per = (double)ms / iters;
+        if (top.ms_per_iteration < 0.0 || per < top.ms_per_iteration) {
+          top = cand;
+          top.ms_per_iteration = per;
+        }
+      }
+  *best = top;
+  const TuneKey key{params->N, params->Np, params->real_type, params->amp_type, pl->R};
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& kv : g_tune)
+    if (kv.first == key) {
+      kv.second = top;
+      return CPRA_OK;
+    }
+  g_tune.push_back({key, top});
+  return CPRA_OK;
 }
 
 // Several plans of one size and precision advanced together, one launch per pass per iteration

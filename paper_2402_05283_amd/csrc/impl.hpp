@@ -18,7 +18,7 @@
 namespace cpra_impl {
 
 struct Layout {
-  size_t P, Pmid, g0, g1, A2, ampscale, maskw, den, tw, coup, alist, iota, errpart, errhist, flags, stage_I,
+  size_t P, Pmid, Pc, g0, g1, A2, ampscale, maskw, den, tw, coup, alist, iota, errpart, errhist, flags, stage_I,
       stage_S, csr_ptr, csr_cell, csr_ent, csr_w, cnt_inv, plane, prep_part, mtab, swk, ctab, total;
   int zc;   // z-planes per step-D chunk
 };
@@ -63,6 +63,8 @@ struct cpra_plan_s {
   bool use_graphs = false;
   // slots per chunk of the chunk-major order inside an episode (0: all slots in every launch)
   int chunk = 0;
+  // the row pass's tile height: RowCfg's (false) or twice it (true); set by a tuning
+  bool row_alt = false;
   // step-D insertion tables, built on the host at the first step-D call; the host copies stay
   // here while their uploads may be in flight
   bool stepd_ready = false;
@@ -141,6 +143,7 @@ struct Ops {
   void (*couple_taps)(cpra_plan_t, const int*, int, int, int);
   void (*refine)(cpra_plan_t, const RefineArgs&);
   void (*fused_step)(cpra_plan_t const*, int, bool, int, double, hipStream_t);
+  void (*synth)(cpra_plan_t, int, int, uint64_t);
 };
 
 template <int N, typename T, typename AP>
@@ -181,7 +184,7 @@ struct Impl {
   // one iteration of the listed slots; couple: Eq. 4 on the way in, from buffer cur into the other
   // buffer (Jacobi) or, with inplace, within buffer cur (the neighbours must not be listed)
   // pin / gbuf (when non-NULL / >= 0): column-pass input spectra and the g buffer to run on,
-  // instead of P and buffer cur (a K-tap boundary couples into the Pmid scratch first)
+  // instead of P and buffer cur (a K-tap boundary couples into the Pc planes first)
   static void step(cpra_plan_t pl, const int* al, int nact, bool couple, bool inplace, int mode, double beta,
                    double* errpart, const void* pin, int gbuf) {
     using CG = ColGeom<N>;
@@ -220,10 +223,20 @@ struct Impl {
     const int gb = gbuf >= 0 ? gbuf : pl->cur;
     T* gin = at<T>(pl, gb ? pl->L.g1 : pl->L.g0);
     T* gout = (couple && !inplace) ? at<T>(pl, gb ? pl->L.g0 : pl->L.g1) : gin;
-    dim3 gr(N / RG::RPB, nact), br(RG::T * RG::RPB);
-    auto row = couple ? k_row<N, T, true> : k_row<N, T, false>;
-    row<<<gr, br, 0, pl->stream>>>(at<C>(pl, pl->L.Pmid), at<C>(pl, pl->L.P), gin, gout, at<uint32_t>(pl, pl->L.maskw),
-                                   at<C>(pl, pl->L.tw), al, cp, pl->p.Np, mode, (T)beta, pl->p.positivity);
+    // the row pass with the plan's tile height (results do not depend on it)
+    auto row = [&](auto kern, int rpb) {
+      kern<<<dim3(N / rpb, nact), dim3(RG::T * rpb), 0, pl->stream>>>(
+          at<C>(pl, pl->L.Pmid), at<C>(pl, pl->L.P), gin, gout, at<uint32_t>(pl, pl->L.maskw), at<C>(pl, pl->L.tw), al,
+          cp, pl->p.Np, mode, (T)beta, pl->p.positivity);
+    };
+    constexpr int R0 = RowRows<N, 0>::RPB, R1 = RowRows<N, 1>::RPB;
+    if (pl->row_alt) {
+      if (couple) row(k_row<N, T, true, R1>, R1);
+      else row(k_row<N, T, false, R1>, R1);
+    } else {
+      if (couple) row(k_row<N, T, true, R0>, R0);
+      else row(k_row<N, T, false, R0>, R0);
+    }
     if (e2) (void)hipEventRecord(e2, pl->stream);
   }
   // E_F partials of the current iterates of the listed slots (column pass without coupling; its
@@ -271,10 +284,10 @@ struct Impl {
     k_shrink_mask<N, T, CB><<<dim3(N, count), 256, 0, pl->stream>>>(buf, list, pm, frac,
                                                                     at<uint32_t>(pl, pl->L.maskw));
   }
-  // Eq. 4 with 2K+1 taps for the listed slots: P -> Pmid, g[gin_buf] -> g[gout_buf]
+  // Eq. 4 with 2K+1 taps for the listed slots: P -> Pc, g[gin_buf] -> g[gout_buf]
   static void couple_taps(cpra_plan_t pl, const int* al, int nact, int gin_buf, int gout_buf) {
     k_couple_taps<N, T><<<dim3(N, nact), 256, 0, pl->stream>>>(
-        at<C>(pl, pl->L.P), at<C>(pl, pl->L.Pmid), at<T>(pl, gin_buf ? pl->L.g1 : pl->L.g0),
+        at<C>(pl, pl->L.P), at<C>(pl, pl->L.Pc), at<T>(pl, gin_buf ? pl->L.g1 : pl->L.g0),
         at<T>(pl, gout_buf ? pl->L.g1 : pl->L.g0), al, at<cpra::Tap>(pl, pl->L.ctab), 2 * pl->K + 1);
   }
   static void refine(cpra_plan_t pl, const RefineArgs& a) {
@@ -349,10 +362,22 @@ struct Impl {
         if (couple) k_col_fused<N, T, AP, true><<<gc, bc, 0, st>>>(ft);
         else k_col_fused<N, T, AP, false><<<gc, bc, 0, st>>>(ft);
       }
-      dim3 gr(N / RG::RPB, tot), br(RG::T * RG::RPB);
-      if (couple) k_row_fused<N, T, AP, true><<<gr, br, 0, st>>>(ft, mode, (T)beta);
-      else k_row_fused<N, T, AP, false><<<gr, br, 0, st>>>(ft, mode, (T)beta);
+      constexpr int R0 = RowRows<N, 0>::RPB, R1 = RowRows<N, 1>::RPB;
+      const int rpb = pls[b0]->row_alt ? R1 : R0;
+      dim3 gr(N / rpb, tot), br(RG::T * rpb);
+      if (pls[b0]->row_alt) {
+        if (couple) k_row_fused<N, T, AP, true, R1><<<gr, br, 0, st>>>(ft, mode, (T)beta);
+        else k_row_fused<N, T, AP, false, R1><<<gr, br, 0, st>>>(ft, mode, (T)beta);
+      } else {
+        if (couple) k_row_fused<N, T, AP, true, R0><<<gr, br, 0, st>>>(ft, mode, (T)beta);
+        else k_row_fused<N, T, AP, false, R0><<<gr, br, 0, st>>>(ft, mode, (T)beta);
+      }
     }
+  }
+  // a synthetic scan of `count` angles from `first` into the plan's staging buffers (autotuning)
+  static void synth(cpra_plan_t pl, int first, int count, uint64_t seed) {
+    k_synth_scan<N><<<dim3(N, count), 256, 0, pl->stream>>>(at<float>(pl, pl->L.stage_I),
+                                                           at<uint8_t>(pl, pl->L.stage_S), first, seed);
   }
   static void assemble(cpra_plan_t pl, void* vol) {
     stepd_run<N, T>(at<C>(pl, pl->L.P), at<CellRec>(pl, pl->L.csr_cell), at<int>(pl, pl->L.csr_ent),
@@ -369,7 +394,7 @@ template <int N, typename T, typename AP> Ops ops_for() {
              &Impl<N, T, AP>::step,     &Impl<N, T, AP>::assemble, &Impl<N, T, AP>::reload,
              &Impl<N, T, AP>::colerr,   &Impl<N, T, AP>::moments,  &Impl<N, T, AP>::twin,
              &Impl<N, T, AP>::merge_avg, &Impl<N, T, AP>::shrinkwrap, &Impl<N, T, AP>::couple_taps,
-             &Impl<N, T, AP>::refine, &Impl<N, T, AP>::fused_step};
+             &Impl<N, T, AP>::refine, &Impl<N, T, AP>::fused_step, &Impl<N, T, AP>::synth};
 }
 
 

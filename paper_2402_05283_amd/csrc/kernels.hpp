@@ -54,6 +54,12 @@ template <> struct RowCfg<192> { static constexpr int F1 = 4, F2 = 24, RPB = 32;
 template <> struct RowCfg<384> { static constexpr int F1 = 8, F2 = 24, RPB = 8; };
 template <> struct RowCfg<512> { static constexpr int F1 = 16, F2 = 16, RPB = 8; };
 template <> struct RowCfg<1024> { static constexpr int F1 = 16, F2 = 32, RPB = 8; };
+// The row pass is compiled for two tile heights (rows per workgroup): RowCfg's and twice it; the
+// autotuner measures both per shape.  RowRows<N, 0> is the default, RowRows<N, 1> the other.
+template <int N, int V> struct RowRows {
+  static constexpr int RPB = V == 0 ? RowCfg<N>::RPB : 2 * RowCfg<N>::RPB;
+  static_assert(RowCfg<N>::F1 * RPB <= 256, "row workgroup size");
+};
 
 template <int N> struct RowGeom {
   static constexpr int L = N / 2;
@@ -988,7 +994,7 @@ __device__ __forceinline__ C partner_c(C v, int partner_lane_idx) {
 // exchange, F1-point IDFT) -> g' in the space layout; real-space update with
 // the support bits and g; R2C back (F1-point DFT, twiddle, LDS exchange,
 // F2-point DFT, post-processing) -> P.
-template <int N, typename T, bool CPL>
+template <int N, typename T, bool CPL, int RPB>
 __device__ __forceinline__ void row_body(const cx<T>* __restrict__ Pmid, cx<T>* __restrict__ P, const T* gin,
                                          T* gout, const uint32_t* __restrict__ maskw,
                                          const cx<T>* __restrict__ tw, int n, const Coupling* __restrict__ coup,
@@ -997,7 +1003,7 @@ __device__ __forceinline__ void row_body(const cx<T>* __restrict__ Pmid, cx<T>* 
   using TL = TwLayout<N>;
   using C = cx<T>;
   constexpr int F1 = Gm::F1, F2 = Gm::F2, TT = Gm::T, SPT = Gm::SPT, H = N / 2;
-  constexpr int RPB = Gm::RPB, MW = Gm::MW;
+  constexpr int MW = Gm::MW;
   constexpr int LS = F1 + Gm::PADR;       // lds stride per m2
   __shared__ C lds[RPB * Gm::RSTRIDE];
   const int tau = threadIdx.x % TT;       // owned frequency class k1 = tau
@@ -1188,12 +1194,12 @@ __device__ __forceinline__ void row_body(const cx<T>* __restrict__ Pmid, cx<T>* 
   }
 }
 
-template <int N, typename T, bool CPL = false>
-__global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((amdgpu_waves_per_eu(4)))
+template <int N, typename T, bool CPL = false, int RPB = RowCfg<N>::RPB>
+__global__ void __launch_bounds__(RowCfg<N>::F1* RPB) __attribute__((amdgpu_waves_per_eu(4)))
     k_row(const cx<T>* __restrict__ Pmid, cx<T>* __restrict__ P, const T* gin, T* gout,
           const uint32_t* __restrict__ maskw, const cx<T>* __restrict__ tw, const int* __restrict__ alist,
           const Coupling* __restrict__ coup, int npd, int mode, T beta, int positivity) {
-  row_body<N, T, CPL>(Pmid, P, gin, gout, maskw, tw, alist[blockIdx.y], coup, npd, mode, beta, positivity);
+  row_body<N, T, CPL, RPB>(Pmid, P, gin, gout, maskw, tw, alist[blockIdx.y], coup, npd, mode, beta, positivity);
 }
 
 // ---------------------------------------------------------------- fused launches
@@ -1247,14 +1253,32 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C) k_col_fused(const
                                     nullptr, 0);
 }
 
-template <int N, typename T, typename AP, bool CPL>
-__global__ void __launch_bounds__(RowCfg<N>::F1* RowCfg<N>::RPB) __attribute__((amdgpu_waves_per_eu(4)))
+template <int N, typename T, typename AP, bool CPL, int RPB = RowCfg<N>::RPB>
+__global__ void __launch_bounds__(RowCfg<N>::F1* RPB) __attribute__((amdgpu_waves_per_eu(4)))
     k_row_fused(const FuseTab<T, AP> ft, int mode, T beta) {
   const int i = blockIdx.y;
   const int p = fuse_plan_of(ft.start, ft.count, i);
   const FusePlan<T, AP>& q = ft.p[p];
-  row_body<N, T, CPL>(q.Pmid, q.P, q.gin, q.gout, q.maskw, q.tw, q.alist[i - ft.start[p]],
+  row_body<N, T, CPL, RPB>(q.Pmid, q.P, q.gin, q.gout, q.maskw, q.tw, q.alist[i - ft.start[p]],
                       q.coup, q.npd, mode, beta, q.positivity);
+}
+
+// ---------------------------------------------------------------- autotuning input
+// A synthetic scan for timing the passes: intensities (u24 / 2^24)^4 * 1e4 from SplitMix64 at
+// counter (n * N + w) * N + u, and a centred disc support of radius 0.3 N.  count angles from
+// `first`, written [i][w][u] and [i][z][t].  The values only need to be finite and non-trivial.
+template <int N>
+__global__ void __launch_bounds__(256) k_synth_scan(float* __restrict__ I, uint8_t* __restrict__ S, int first,
+                                                    uint64_t seed) {
+  const int i = blockIdx.y, w = blockIdx.x;
+  const float r2 = 0.09f * (float)N * (float)N;
+  for (int u = threadIdx.x; u < N; u += blockDim.x) {
+    const uint64_t cnt = ((uint64_t)(first + i) * N + (uint64_t)w) * N + (uint64_t)u;
+    const float x = (float)(splitmix64_at(seed, cnt) >> 40) * (1.0f / 16777216.0f);
+    I[((size_t)i * N + w) * N + u] = 1e4f * (x * x) * (x * x);
+    const float dz = (float)(w - N / 2), dt = (float)(u - N / 2);
+    S[((size_t)i * N + w) * N + u] = (dz * dz + dt * dt) < r2 ? 1 : 0;
+  }
 }
 
 // ---------------------------------------------------------------- error reduce

@@ -687,6 +687,38 @@ def test_async_submit(torch):
     assert e.value.status == -4                    # poisoned
 
 
+@pytest.mark.parametrize("N", [64, 512])
+def test_tuning_keeps_results(torch, N):
+    """Every launch choice the autotuner picks between (row-pass tile height, chunk-major order,
+    graph episodes) gives the same objects bit for bit; cpra_autotune returns one of them and
+    plans of the tuned shape created afterwards start with it."""
+    import paper_2402_05283_amd as cp
+    Np = 8 if N == 64 else 3
+    scan = make_scan(1, N=N, Np=Np)
+    I = torch.from_numpy(scan["I"]).cuda()
+    S = torch.from_numpy(scan["support"]).cuda()
+    banner(f"tuning choices N={N}")
+    res = []
+    for rt, ch, gr in ((0, 0, 0), (1, 0, 0), (1, 3, 1), (0, 2, 1)):
+        p = cp.Plan(N, Np, theta=scan["theta"], n_ei=5, seed=scan["phase_seed"])
+        p.set_tuning(rt, ch, gr)
+        p.submit(0, I, S)
+        p.iterate(12, cp.HIO, 0.9)
+        p.iterate(3, cp.ER, 0.0)
+        torch.cuda.synchronize()
+        res.append(p.objects().cpu().numpy())
+    for r in res[1:]:
+        assert np.array_equal(r, res[0])
+    banner(f"autotune N={N}")
+    best = cp.autotune(N, Np, n_iter=10, n_ei=5)
+    print("autotune", N, Np, best)
+    assert best["row_tile"] in (0, 1) and best["graphs"] in (0, 1) and best["ms_per_iteration"] > 0
+    p = cp.Plan(N, Np, n_ei=5)
+    p.submit(0, I, S)
+    p.iterate(5, cp.HIO, 0.9)
+    torch.cuda.synchronize()
+
+
 def test_api_errors(torch):
     import paper_2402_05283_amd as cp
     scan = make_scan(1, Np=4)
