@@ -221,6 +221,49 @@ def summarize_pmc(fetch_dir, write_dir, cmd):
     return "\n".join(lines) + "\n"
 
 
+def summarize_sq(sq_dir, cmd):
+    """Markdown summary of a rocprofv3 --pmc run of SQ counters: per kernel of the iteration and of
+    step D, VALU instructions per wave, the share of wave time spent waiting on instruction
+    dependencies (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) and issuing VALU (SQ_ACTIVE_INST_VALU /
+    SQ_WAVE_CYCLES), and the average resident waves per CU (SQ_WAVE_CYCLES counts every 4 cycles,
+    GRBM_GUI_ACTIVE sums the 8 XCDs)."""
+    import re
+    acc = {}
+    for r in _pmc_rows(sq_dir):
+        m = re.search(r"cpra::(k_col_pair|k_row|k_stepd_rows|k_stepd_cols)<512, float[^(]*?(?:, (true|false))?[,>]",
+                      r["Kernel_Name"])
+        if not m:
+            continue
+        name = r["Kernel_Name"]
+        key = m.group(1)
+        if key == "k_col_pair":
+            if ", 0, false, false>" not in name:
+                continue
+        if key == "k_row":
+            if "false" not in name.split("k_row<")[1].split(">")[0]:
+                continue
+        acc.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    lines = ["# SQ counters of the iteration and step-D kernels: N=512, Np=360 cell scan", "",
+             "Command (repo root, one MI355X):", "", f"    {cmd}", "",
+             "Per launch averages (plain column and row passes: no coupling, no error history).  "
+             "VALU busy = VALU instructions x 4 cycles / (1024 SIMDs x launch cycles).", "",
+             "| Kernel | Launches | Waves | VALU instr / wave | Dependency waits / wave time | VALU issue / wave time | "
+             "Waves resident per CU | VALU busy |", "|---|---|---|---|---|---|---|---|"]
+    for k in ("k_col_pair", "k_row", "k_stepd_rows", "k_stepd_cols"):
+        a = acc.get(k)
+        if not a:
+            continue
+        mean = {c: sum(v) / len(v) for c, v in a.items()}
+        w = mean["SQ_WAVES"]
+        cyc = mean["GRBM_GUI_ACTIVE"] / 8.0
+        resident = 4.0 * mean["SQ_WAVE_CYCLES"] / (256.0 * cyc)
+        busy = mean["SQ_INSTS_VALU"] * 4.0 / (1024.0 * cyc)
+        lines.append(f"| {k} | {len(a['SQ_WAVES'])} | {w:.0f} | {mean['SQ_INSTS_VALU'] / w:.0f} | "
+                     f"{mean['SQ_WAIT_INST_ANY'] / mean['SQ_WAVE_CYCLES']:.2f} | "
+                     f"{mean['SQ_ACTIVE_INST_VALU'] / mean['SQ_WAVE_CYCLES']:.2f} | {resident:.1f} | {busy:.2f} |")
+    return "\n".join(lines) + "\n"
+
+
 def summarize_trace(trace_dir, bench_json, cmd):
     """Markdown summary of a `rocprofv3 --kernel-trace --stats` run of bench.py, beside the
     launch durations that bench.py measured itself with HIP events in the same run."""
@@ -742,12 +785,20 @@ def main():
                     help="print the traffic summary of two rocprofv3 --pmc runs and exit")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
                     help="print the kernel-trace summary of a rocprofv3 --stats run and exit")
+    ap.add_argument("--summarize-sq", metavar="SQ_DIR", help="print the SQ-counter summary of a rocprofv3 --pmc run")
     args = ap.parse_args()
     if args.summarize_trace:
         cmd = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace -o run "
                "-- python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-compare --guesses 0 --serve-scans 0 --batch-scans 0 "
                "> gpurun_out/trace_bench.json")
         print(summarize_trace(*args.summarize_trace, cmd), end="")
+        return
+    if args.summarize_sq:
+        cmd = ("timeout -s KILL 180 rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU "
+               "SQ_WAIT_INST_ANY SQ_INSTS_VMEM_RD SQ_INSTS_VALU SQ_WAIT_ANY GRBM_GUI_ACTIVE --output-format csv "
+               "-d gpurun_out/sq -o run -- python3 bench.py --steps 1 --warmup 0 --iters 20 --no-cpu-baseline "
+               "--serve-scans 0 --no-compare --guesses 0 --batch-scans 0 --no-autotune")
+        print(summarize_sq(args.summarize_sq, cmd), end="")
         return
     if args.summarize_pmc:
         cmd = ("timeout -s KILL 120 rocprofv3 --pmc {counter} --output-format csv -d gpurun_out/{out} -o run "

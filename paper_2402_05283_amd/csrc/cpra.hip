@@ -190,6 +190,7 @@ Layout layout_of(const cpra_params* p) {
   L.cnt_inv = take(N * N * rs);
   L.zc = stepd_chunk(p->N);
   L.plane = take((size_t)L.zc * N * N * cs);
+  L.stage_T = take((size_t)L.zc * Np * H * cs);   // step D: a chunk's rows of every angle, plane-major
   L.prep_part = take(Np * cpra::kPrepBlocks * 12);
   L.mtab = take(S * 3 * 8 + S * 4 * 4 + (S / Np) * 64 + 256);   // step C tables
   L.swk = take((N + 1) * rs);                                      // shrinkwrap window taps

@@ -19,7 +19,7 @@ namespace cpra_impl {
 
 struct Layout {
   size_t P, Pmid, Pc, g0, g1, A2, ampscale, maskw, den, tw, coup, alist, iota, errpart, errhist, flags, stage_I,
-      stage_S, csr_ptr, csr_cell, csr_ent, csr_w, cnt_inv, plane, prep_part, mtab, swk, ctab, total;
+      stage_S, csr_ptr, csr_cell, csr_ent, csr_w, cnt_inv, plane, stage_T, prep_part, mtab, swk, ctab, total;
   int zc;   // z-planes per step-D chunk
 };
 
@@ -380,7 +380,8 @@ struct Impl {
                                                            at<uint8_t>(pl, pl->L.stage_S), first, seed);
   }
   static void assemble(cpra_plan_t pl, void* vol) {
-    stepd_run<N, T>(at<C>(pl, pl->L.P), at<CellRec>(pl, pl->L.csr_cell), at<int>(pl, pl->L.csr_ent),
+    stepd_run<N, T>(at<C>(pl, pl->L.P), pl->p.Np, at<C>(pl, pl->L.stage_T), at<CellRec>(pl, pl->L.csr_cell),
+                    at<int>(pl, pl->L.csr_ent),
                     pl->p.insertion == CPRA_INSERT_BILINEAR ? at<T>(pl, pl->L.csr_w) : nullptr,
                     at<T>(pl, pl->L.cnt_inv), at<C>(pl, pl->L.tw), at<C>(pl, pl->L.plane), pl->L.zc,
                     reinterpret_cast<T*>(vol), pl->stream);

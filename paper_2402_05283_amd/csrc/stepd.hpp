@@ -32,6 +32,30 @@ template <int N, typename T> constexpr int stepd_lines(int want, size_t per_line
   return k;
 }
 
+// Staging of a chunk of z-planes: rows z0 .. z0+nz-1 of every angle's packed half spectrum into
+// Tz[zi][n][j] (contiguous per plane), so that the gather of one plane reads one contiguous block
+// of N_p N/2 values instead of N_p rows scattered over the angles' planes.  grid (nz, Np).
+template <int N, typename T>
+__global__ void __launch_bounds__(256) k_stepd_stage(const cx<T>* __restrict__ P, cx<T>* __restrict__ Tz, int z0,
+                                                     int Np) {
+  constexpr int H = N / 2;
+  const int zi = blockIdx.x, n = blockIdx.y;
+  const cx<T>* Pn = P + (size_t)n * N * H;
+  cx<T>* out = Tz + ((size_t)zi * Np + n) * H;
+  for (int j = threadIdx.x; j < H; j += blockDim.x) out[j] = Pn[pix<N>(z0 + zi, j)];
+}
+
+// S[u] of one row from its packed half spectrum row Pr[j] (j < N/2; P[0] = S[0] + i S[N/2])
+template <int N, typename T>
+__device__ __forceinline__ cx<T> spectrum_row_at(const cx<T>* Pr, int u) {
+  constexpr int H = N / 2;
+  using C = cx<T>;
+  if (u == 0) return mk<C>(Pr[0].x, (T)0);
+  if (u == H) return mk<C>(Pr[0].y, (T)0);
+  if (u < H) return Pr[u];
+  return conj(Pr[N - u]);
+}
+
 // S[z][u] of an angle from its packed half spectrum Pn (layout pix<N>)
 template <int N, typename T>
 __device__ __forceinline__ cx<T> spectrum_at(const cx<T>* Pn, int z, int u) {
@@ -54,9 +78,9 @@ struct CellRec {
 // Block: RB rows x R1 threads; grid: (N / RB) * nz (see the mapping below).
 template <int N, typename T, int RB>
 __global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
-    k_stepd_rows(const cx<T>* __restrict__ P, const CellRec* __restrict__ cells, const int* __restrict__ ent,
-                 const T* __restrict__ wts, const T* __restrict__ cnt_inv, const cx<T>* __restrict__ tw,
-                 cx<T>* __restrict__ plane, int z0, int nz) {
+    k_stepd_rows(const cx<T>* __restrict__ Tz, int Np, const CellRec* __restrict__ cells,
+                 const int* __restrict__ ent, const T* __restrict__ wts, const T* __restrict__ cnt_inv,
+                 const cx<T>* __restrict__ tw, cx<T>* __restrict__ plane, int nz) {
   using C = cx<T>;
   constexpr int R1 = StepdCfg<N>::R1, R2 = StepdCfg<N>::R2, Q = R2 / R1, H = N / 2;
   static_assert(R1 * R2 == N && Q >= 1 && R2 % R1 == 0, "step D decomposition");
@@ -79,12 +103,12 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
     kyb = L % KB;
   }
   const int ky = kyb * RB + r;
-  const int z = z0 + zi;
+  const C* Tp = Tz + (size_t)zi * Np * H;   // this plane's rows of every angle
   C* L0 = lds + r * R2 * LS;
   C v[R2];
   auto sample = [&](int e, int code) CPRA_INLINE -> C {
     const int n = code / N, u = code % N;
-    C s = spectrum_at<N, T>(P + (size_t)n * N * H, z, u);
+    C s = spectrum_row_at<N, T>(Tp + (size_t)n * H, u);
     if (u & 1) { s.x = -s.x; s.y = -s.y; }
     if (wts) s = cscale(s, wts[e]);      // bilinear insertion weight
     return s;
@@ -168,15 +192,16 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* CC)
 
 // tw: W_N^j, j < N (the first N entries of the plan's twiddle table)
 template <int N, typename T>
-void stepd_run(const cx<T>* P, const CellRec* cells, const int* ent, const T* wts, const T* cnt_inv,
-               const cx<T>* tw, cx<T>* plane, int zc, T* vol, hipStream_t st) {
+void stepd_run(const cx<T>* P, int Np, cx<T>* Tz, const CellRec* cells, const int* ent, const T* wts,
+               const T* cnt_inv, const cx<T>* tw, cx<T>* plane, int zc, T* vol, hipStream_t st) {
   constexpr int R1 = StepdCfg<N>::R1, R2 = StepdCfg<N>::R2;
   // rows / columns per workgroup: up to 256 threads, LDS within 128 KiB
   constexpr int RB = stepd_lines<N, T>(256 / R1 < N ? 256 / R1 : N, (size_t)R2 * (R1 + 1));
   constexpr int CC = stepd_lines<N, T>(256 / R1 < N ? 256 / R1 : N, (size_t)R2 * R1);
   for (int z0 = 0; z0 < N; z0 += zc) {
     const int nz = (N - z0) < zc ? (N - z0) : zc;
-    k_stepd_rows<N, T, RB><<<(N / RB) * nz, R1 * RB, 0, st>>>(P, cells, ent, wts, cnt_inv, tw, plane, z0, nz);
+    k_stepd_stage<N, T><<<dim3(nz, Np), 256, 0, st>>>(P, Tz, z0, Np);
+    k_stepd_rows<N, T, RB><<<(N / RB) * nz, R1 * RB, 0, st>>>(Tz, Np, cells, ent, wts, cnt_inv, tw, plane, nz);
     k_stepd_cols<N, T, CC><<<dim3(N / CC, nz), R1 * CC, 0, st>>>(plane, tw, vol, z0);
   }
 }
