@@ -340,7 +340,8 @@ def serving_latency(cp, torch, scan, I, S, args, cache):
                                   seed=scan["phase_seed"] + 1 + len(jobs), theta=np.pi * np.arange(npp) / npp))
             t += npp / args.serve_fps + 0.25
     T = max(j.t_start + j.Np / j.fps for j in jobs)
-    srv = serve.Server(200 << 30, n_ei=N_EI, r_frame=N_EI, r_final=50, algo=cp.HIO, beta=BETA)
+    srv = serve.Server(200 << 30, n_ei=N_EI, r_frame=N_EI, r_final=50, algo=cp.HIO, beta=BETA,
+                       hold_others=not args.serve_no_hold, depth=args.serve_depth)
     prev_fuse = cp.set_batch_fusion(args.serve_fusion) if args.serve_fusion is not None else None
     print(f"[bench] serving {len(jobs)} scans on {args.serve_scans} lanes at {args.serve_fps} frames/s each "
           f"(~{T:.0f} s)", file=sys.stderr, flush=True)
@@ -361,6 +362,12 @@ def serving_latency(cp, torch, scan, I, S, args, cache):
     work = sum(d.iters_done * d.Np for d in done)
     print(f"[bench] serving done in {wall:.1f} s; latency p50 {np.percentile(lat, 50):.1f} ms, "
           f"max {lat.max():.1f} ms", file=sys.stderr, flush=True)
+    worst = []
+    for i in np.argsort(-lat)[:5]:
+        d = done[i]
+        ms = lambda t: None if t is None else round((t - d.t_last_frame) * 1e3, 1)
+        worst.append({"N": d.N, "Np": d.Np, "latency_ms": round(float(lat[i]), 1), "last_submit_ms": ms(d.t_last_submit),
+                      "last_issue_ms": ms(d.t_last_issue), "step_d_issue_ms": ms(d.t_assemble)})
     by_shape = {}
     for d, l in zip(done, lat):
         by_shape.setdefault(f"N={d.N},Np={d.Np}", []).append(l)
@@ -374,7 +381,8 @@ def serving_latency(cp, torch, scan, I, S, args, cache):
                     f"N in {{256, 512, 1024}}, N_p in {{180, 360}} (1024 with 180), Poisson 1e6 data, "
                     f"{args.serve_fps:g} frames/s per scan, 10 HIO iterations per landed frame (partial angle sets), "
                     f"50 after the last, then step D",
-            "shared_launches_up_to_N": fuse,
+            "shared_launches_up_to_N": fuse, "hold_others": srv.hold_others, "depth": srv.depth,
+            "worst": worst, "longest_round_ms": round(srv.step_max_s * 1e3, 1), "rounds_over_50ms": int(srv.slow_steps),
             "serving_wall_s": round(wall, 2), "pattern_iterations": int(work),
             "pattern_iterations_per_s": round(work / wall, 1)}
 
@@ -771,6 +779,10 @@ def main():
     ap.add_argument("--serve-scans", type=int, default=8, help="detector lanes of the serving leg (0: skip)")
     ap.add_argument("--serve-per-lane", type=int, default=13,
                     help="scans per lane (latency samples = lanes x scans per lane)")
+    ap.add_argument("--serve-depth", type=int, default=1,
+                    help="serving: episodes in flight per scan before its last frame has landed")
+    ap.add_argument("--serve-no-hold", action="store_true",
+                    help="serving: other scans keep issuing while a scan whose last frame has landed is unfinished")
     ap.add_argument("--serve-fps", type=float, default=20.0, help="frames per second per scan")
     ap.add_argument("--serve-fusion", type=int, default=None,
                     help="size limit of shared launches in the serving leg (cpra_set_batch_fusion; default: "

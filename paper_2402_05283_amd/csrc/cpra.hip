@@ -7,6 +7,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -290,12 +292,14 @@ cpra_status upload_tables(cpra_plan_t pl) {
     }
   // the device tables are copied from the plan's pinned staging buffer, without synchronising the
   // stream: the copies are ordered behind the launches that read the previous tables, and the
-  // staging buffer is rewritten only after the previous upload has completed (ev_tab)
-  if (pl->tab_pending) {
-    HIPCHK(pl, hipEventSynchronize(pl->ev_tab));
-    pl->tab_pending = false;
+  // staging slot is rewritten only after its previous upload, kTabSlots uploads back, has completed
+  const int slot = pl->tab_next;
+  pl->tab_next = (slot + 1) % cpra_plan_s::kTabSlots;
+  if (pl->tab_pending[slot]) {
+    HIPCHK(pl, hipEventSynchronize(pl->ev_tab[slot]));
+    pl->tab_pending[slot] = false;
   }
-  char* hb = reinterpret_cast<char*>(pl->h_tab);
+  char* hb = reinterpret_cast<char*>(pl->h_tab) + (size_t)slot * pl->tab_bytes;
   std::memcpy(hb, pl->coup_h.data(), pl->coup_h.size() * sizeof(cpra::Coupling));
   HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.coup, hb, pl->coup_h.size() * sizeof(cpra::Coupling),
                             hipMemcpyHostToDevice, pl->stream));
@@ -320,14 +324,47 @@ cpra_status upload_tables(cpra_plan_t pl) {
     std::memcpy(hb, pl->alist_h.data(), pl->alist_h.size() * 4);
     HIPCHK(pl, hipMemcpyAsync(pl->ws + pl->L.alist, hb, pl->alist_h.size() * 4, hipMemcpyHostToDevice, pl->stream));
   }
-  HIPCHK(pl, hipEventRecord(pl->ev_tab, pl->stream));
-  pl->tab_pending = true;
+  HIPCHK(pl, hipEventRecord(pl->ev_tab[slot], pl->stream));
+  pl->tab_pending[slot] = true;
   pl->tables_dirty = false;
   pl->table_version += 1;
   return CPRA_OK;
 }
 
 }  // namespace
+
+namespace cpra_impl {
+namespace {
+std::mutex g_pin_mu;
+std::multimap<size_t, void*> g_pin_free;   // size class -> idle pinned buffer
+size_t pin_class(size_t bytes) {
+  size_t c = size_t(4) << 10;
+  while (c < bytes) c <<= 1;
+  return c;
+}
+}  // namespace
+
+void* pinned_take(size_t bytes) {
+  const size_t c = pin_class(bytes);
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    auto it = g_pin_free.find(c);
+    if (it != g_pin_free.end()) {
+      void* p = it->second;
+      g_pin_free.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  return hipHostMalloc(&p, c, hipHostMallocDefault) == hipSuccess ? p : nullptr;
+}
+
+void pinned_give(void* p, size_t bytes) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free.emplace(pin_class(bytes), p);
+}
+}  // namespace cpra_impl
 
 extern "C" {
 
@@ -385,9 +422,12 @@ cpra_status cpra_plan(const cpra_params* params, void* workspace, size_t workspa
   const size_t S = (size_t)params->Np * pl->R;
   const size_t tab_bytes = align_up(S * sizeof(cpra::Coupling)) +
                            align_up(pl->K > 1 ? S * (2 * pl->K + 1) * sizeof(cpra::Tap) : 0) + S * 4;
-  e = hipHostMalloc(&pl->h_tab, tab_bytes, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&pl->h_flag, 256, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_tab, hipEventDisableTiming);
+  pl->tab_bytes = align_up(tab_bytes);
+  pl->h_tab = pinned_take(pl->tab_bytes * cpra_plan_s::kTabSlots);
+  pl->h_flag = static_cast<int32_t*>(pinned_take(256));
+  if (!pl->h_tab || !pl->h_flag) e = hipErrorOutOfMemory;
+  for (int i = 0; i < cpra_plan_s::kTabSlots && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&pl->ev_tab[i], hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_flag, hipEventDisableTiming);
   std::vector<int32_t> iota(S);
   std::iota(iota.begin(), iota.end(), 0);
@@ -427,49 +467,110 @@ cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t 
 }
 
 // Step-D tables: the integer cell map of the Fourier-slice insertion (built on the host in FP64),
-// the bilinear weights, and the inverse count (or weight sum) per cell.  Built at the first step-D
-// call rather than at plan creation, so that this host work overlaps the iterations already
-// queued on the stream; the uploads are ordered on the stream before step D's kernels.
+// the bilinear weights, and the inverse count (or weight sum) per cell, packed into one pinned
+// image: row pointers, cell records, entries, weights, inverse counts, each 256-byte aligned.  The
+// image depends only on N, Np, the angles, the insertion and the precision, so a process keeps the
+// images of up to kStepdImages shapes and later plans of a shape upload the same image (scans of a
+// serving mix repeat a few shapes).  Built at the first step-D call rather than at plan creation,
+// so that this host work overlaps the iterations already queued on the stream; the uploads come
+// from pinned memory, so they are ordered on the stream before step D's kernels without the host
+// waiting for the iterations ahead of them.
+namespace {
+struct StepdImage {
+  int N = 0, Np = 0;
+  bool bil = false, f64 = false;
+  std::vector<double> theta;
+  void* host = nullptr;        // pinned
+  size_t bytes = 0;
+  size_t piece[5] = {};        // bytes of each piece, in image order
+};
+constexpr size_t kStepdImages = 16;
+std::mutex g_img_mu;
+std::vector<std::shared_ptr<const StepdImage>> g_img;
+
+std::shared_ptr<StepdImage> build_stepd_image(const cpra_params& p, const std::vector<double>& theta) {
+  auto img = std::make_shared<StepdImage>();
+  img->N = p.N;
+  img->Np = p.Np;
+  img->bil = p.insertion == CPRA_INSERT_BILINEAR;
+  img->f64 = p.real_type == CPRA_REAL_F64;
+  img->theta = theta;
+  std::vector<int32_t> rp, ent;
+  std::vector<double> wts;
+  if (img->bil) cpra_host::insertion_csr_bilinear(p.N, p.Np, theta.data(), rp, ent, wts);
+  else cpra_host::insertion_csr(p.N, p.Np, theta.data(), rp, ent);
+  const size_t NN = (size_t)p.N * p.N;
+  std::vector<float> wf(wts.begin(), wts.end());
+  std::vector<double> inv_d(NN);
+  std::vector<float> inv_f(NN);
+  for (size_t c = 0; c < NN; ++c) {
+    double tot = 0.0;   // entry count, or the sum of the bilinear weights (in entry order)
+    for (int i = rp[c]; i < rp[c + 1]; ++i) tot += img->bil ? wts[i] : 1.0;
+    inv_d[c] = tot > 0.0 ? 1.0 / tot : 0.0;
+    inv_f[c] = (float)inv_d[c];
+  }
+  // the cell records of step D's gather: first entry, entry range, inverse count as FP32 bits
+  std::vector<cpra::CellRec> cell(NN);
+  for (size_t c = 0; c < NN; ++c) {
+    cpra::CellRec& r = cell[c];
+    r.begin = rp[c];
+    r.end = rp[c + 1];
+    r.first = rp[c] < rp[c + 1] ? ent[rp[c]] : -1;
+    std::memcpy(&r.inv_bits, &inv_f[c], 4);
+  }
+  const void* src[5] = {rp.data(), cell.data(), ent.data(),
+                        img->f64 ? (const void*)wts.data() : (const void*)wf.data(),
+                        img->f64 ? (const void*)inv_d.data() : (const void*)inv_f.data()};
+  img->piece[0] = rp.size() * 4;
+  img->piece[1] = NN * sizeof(cpra::CellRec);
+  img->piece[2] = ent.size() * 4;
+  img->piece[3] = img->bil ? wts.size() * (img->f64 ? 8 : 4) : 0;
+  img->piece[4] = NN * (img->f64 ? 8 : 4);
+  for (size_t b : img->piece) img->bytes += align_up(b);
+  img->host = pinned_take(img->bytes);
+  if (!img->host) return nullptr;
+  char* hb = static_cast<char*>(img->host);
+  for (int i = 0; i < 5; ++i) {
+    if (img->piece[i]) std::memcpy(hb, src[i], img->piece[i]);
+    hb += align_up(img->piece[i]);
+  }
+  return img;
+}
+}  // namespace
+
 static cpra_status ensure_stepd_tables(cpra_plan_t pl) {
   if (pl->stepd_ready) return CPRA_OK;
   const cpra_params& p = pl->p;
   const bool bil = p.insertion == CPRA_INSERT_BILINEAR;
   const bool f64 = p.real_type == CPRA_REAL_F64;
-  std::vector<int32_t>& rp = pl->csr_rp;
-  std::vector<int32_t>& ent = pl->csr_ent;
-  std::vector<double>& wts = pl->csr_wd;
-  if (bil) cpra_host::insertion_csr_bilinear(p.N, p.Np, pl->theta.data(), rp, ent, wts);
-  else cpra_host::insertion_csr(p.N, p.Np, pl->theta.data(), rp, ent);
-  const size_t NN = (size_t)p.N * p.N;
-  pl->csr_wf.assign(wts.begin(), wts.end());
-  pl->inv_d.resize(NN);
-  pl->inv_f.resize(NN);
-  for (size_t c = 0; c < NN; ++c) {
-    double tot = 0.0;   // entry count, or the sum of the bilinear weights (in entry order)
-    for (int i = rp[c]; i < rp[c + 1]; ++i) tot += bil ? wts[i] : 1.0;
-    pl->inv_d[c] = tot > 0.0 ? 1.0 / tot : 0.0;
-    pl->inv_f[c] = (float)pl->inv_d[c];
+  std::shared_ptr<const StepdImage> img;
+  {
+    std::lock_guard<std::mutex> lk(g_img_mu);
+    for (const auto& m : g_img)
+      if (m->N == p.N && m->Np == p.Np && m->bil == bil && m->f64 == f64 && m->theta == pl->theta) img = m;
+  }
+  if (!img) {
+    std::shared_ptr<StepdImage> built = build_stepd_image(p, pl->theta);
+    if (!built) return fail(pl, CPRA_ERR_DEVICE, "step D: pinned staging of the insertion tables failed");
+    std::lock_guard<std::mutex> lk(g_img_mu);
+    if (g_img.size() < kStepdImages) {
+      g_img.push_back(built);          // kept for the process's lifetime
+    } else {
+      pl->h_stepd = built->host;       // not cached: the plan returns the buffer when it is destroyed
+      pl->stepd_bytes = built->bytes;
+    }
+    img = built;
   }
   const Layout& L = pl->L;
-  HIPCHK(pl, hipMemcpyAsync(pl->ws + L.csr_ptr, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, pl->stream));
-  // the cell records of step D's gather: first entry, entry range, inverse count as FP32 bits
-  pl->cell_h.resize(NN);
-  for (size_t c = 0; c < NN; ++c) {
-    cpra::CellRec& r = pl->cell_h[c];
-    r.begin = rp[c];
-    r.end = rp[c + 1];
-    r.first = rp[c] < rp[c + 1] ? ent[rp[c]] : -1;
-    std::memcpy(&r.inv_bits, &pl->inv_f[c], 4);
+  const size_t dst[5] = {L.csr_ptr, L.csr_cell, L.csr_ent, L.csr_w, L.cnt_inv};
+  HIPCHK(pl, hipEventCreateWithFlags(&pl->ev_stepd, hipEventDisableTiming));
+  const char* hb = static_cast<const char*>(img->host);
+  for (int i = 0; i < 5; ++i) {
+    if (img->piece[i])
+      HIPCHK(pl, hipMemcpyAsync(pl->ws + dst[i], hb, img->piece[i], hipMemcpyHostToDevice, pl->stream));
+    hb += align_up(img->piece[i]);
   }
-  HIPCHK(pl, hipMemcpyAsync(pl->ws + L.csr_cell, pl->cell_h.data(), NN * sizeof(cpra::CellRec), hipMemcpyHostToDevice,
-                            pl->stream));
-  HIPCHK(pl, hipMemcpyAsync(pl->ws + L.csr_ent, ent.data(), ent.size() * 4, hipMemcpyHostToDevice, pl->stream));
-  if (bil) {
-    if (f64) HIPCHK(pl, hipMemcpyAsync(pl->ws + L.csr_w, wts.data(), wts.size() * 8, hipMemcpyHostToDevice, pl->stream));
-    else HIPCHK(pl, hipMemcpyAsync(pl->ws + L.csr_w, pl->csr_wf.data(), wts.size() * 4, hipMemcpyHostToDevice, pl->stream));
-  }
-  if (f64) HIPCHK(pl, hipMemcpyAsync(pl->ws + L.cnt_inv, pl->inv_d.data(), NN * 8, hipMemcpyHostToDevice, pl->stream));
-  else HIPCHK(pl, hipMemcpyAsync(pl->ws + L.cnt_inv, pl->inv_f.data(), NN * 4, hipMemcpyHostToDevice, pl->stream));
+  HIPCHK(pl, hipEventRecord(pl->ev_stepd, pl->stream));
   pl->stepd_ready = true;
   return CPRA_OK;
 }

@@ -23,6 +23,12 @@ struct Layout {
   int zc;   // z-planes per step-D chunk
 };
 
+// Process-wide pool of pinned host buffers.  A plan's staging buffers go back to the pool when it is
+// destroyed instead of to hipHostFree, which waits for every stream of the device; pooled buffers
+// are held until the process ends.  pinned_take returns nullptr if the allocation fails.
+void* pinned_take(size_t bytes);
+void pinned_give(void* p, size_t bytes);
+
 }  // namespace cpra_impl
 
 struct cpra_plan_s {
@@ -65,19 +71,23 @@ struct cpra_plan_s {
   int chunk = 0;
   // the row pass's tile height: RowCfg's (false) or twice it (true); set by a tuning
   bool row_alt = false;
-  // step-D insertion tables, built on the host at the first step-D call; the host copies stay
-  // here while their uploads may be in flight
+  // step-D insertion tables: uploaded at the first step-D call from a pinned image that the
+  // process caches per shape (ev_stepd: the uploads have completed); h_stepd holds the plan's own
+  // image when the cache was full
   bool stepd_ready = false;
-  std::vector<int32_t> csr_rp, csr_ent;
-  std::vector<double> csr_wd, inv_d;
-  std::vector<float> csr_wf, inv_f;
-  std::vector<cpra::CellRec> cell_h;
+  void* h_stepd = nullptr;
+  size_t stepd_bytes = 0;
+  hipEvent_t ev_stepd = nullptr;
   hipStream_t cap_stream = nullptr;
   hipEvent_t ev_batch = nullptr;   // orders a fused batch's stream and the plan's own stream
-  // pinned staging of the coupling tables and slot list (ev_tab: the last upload has completed)
+  // pinned staging of the coupling tables and slot list: a ring of kTabSlots buffers, so that an
+  // upload waits only for the one kTabSlots uploads back (ev_tab[i]: slot i's copies completed)
+  static constexpr int kTabSlots = 4;
   void* h_tab = nullptr;
-  hipEvent_t ev_tab = nullptr;
-  bool tab_pending = false;
+  size_t tab_bytes = 0;
+  hipEvent_t ev_tab[kTabSlots] = {};
+  bool tab_pending[kTabSlots] = {};
+  int tab_next = 0;
   // the data check of asynchronous submits: the device flag copied to pinned memory (ev_flag)
   int32_t* h_flag = nullptr;
   hipEvent_t ev_flag = nullptr;
@@ -98,12 +108,19 @@ struct cpra_plan_s {
     drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (ev_batch) (void)hipEventDestroy(ev_batch);
-    if (tab_pending) (void)hipEventSynchronize(ev_tab);
+    for (int i = 0; i < kTabSlots; ++i)
+      if (tab_pending[i]) (void)hipEventSynchronize(ev_tab[i]);
     if (flag_pending) (void)hipEventSynchronize(ev_flag);
-    if (ev_tab) (void)hipEventDestroy(ev_tab);
+    if (ev_stepd) {
+      (void)hipEventSynchronize(ev_stepd);
+      (void)hipEventDestroy(ev_stepd);
+    }
+    for (hipEvent_t ev : ev_tab)
+      if (ev) (void)hipEventDestroy(ev);
     if (ev_flag) (void)hipEventDestroy(ev_flag);
-    if (h_tab) (void)hipHostFree(h_tab);
-    if (h_flag) (void)hipHostFree(h_flag);
+    cpra_impl::pinned_give(h_tab, tab_bytes * kTabSlots);
+    cpra_impl::pinned_give(h_flag, 256);
+    cpra_impl::pinned_give(h_stepd, stepd_bytes);
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
   }
 };

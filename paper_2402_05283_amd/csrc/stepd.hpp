@@ -45,17 +45,6 @@ __global__ void __launch_bounds__(256) k_stepd_stage(const cx<T>* __restrict__ P
   for (int j = threadIdx.x; j < H; j += blockDim.x) out[j] = Pn[pix<N>(z0 + zi, j)];
 }
 
-// S[u] of one row from its packed half spectrum row Pr[j] (j < N/2; P[0] = S[0] + i S[N/2])
-template <int N, typename T>
-__device__ __forceinline__ cx<T> spectrum_row_at(const cx<T>* Pr, int u) {
-  constexpr int H = N / 2;
-  using C = cx<T>;
-  if (u == 0) return mk<C>(Pr[0].x, (T)0);
-  if (u == H) return mk<C>(Pr[0].y, (T)0);
-  if (u < H) return Pr[u];
-  return conj(Pr[N - u]);
-}
-
 // S[z][u] of an angle from its packed half spectrum Pn (layout pix<N>)
 template <int N, typename T>
 __device__ __forceinline__ cx<T> spectrum_at(const cx<T>* Pn, int z, int u) {
@@ -74,23 +63,78 @@ struct CellRec {
   int first, begin, end, inv_bits;
 };
 
-// Rows: gather Q_z[ky][:] and inverse transform along kx.
-// Block: RB rows x R1 threads; grid: (N / RB) * nz (see the mapping below).
+// Gather: Q_z[ky][kx] = (-1)^(ky+kx) / cnt(ky,kx) * sum over the cell's entries (n, u) of
+// (-1)^u S_n[z][u] (bilinear: weighted), one thread per cell, into the plane buffer.  No LDS, so
+// many waves are resident to hide the dependent loads.  A cell's entries are summed in CSR order,
+// their loads issued eight at a time (the cells near k = 0 hold many: the zero-frequency cell one
+// per angle).  1D grid of (N^2 / 256) * nz workgroups; XCD x (workgroup L mod 8) takes planes
+// [x nz/8, (x+1) nz/8) whole, so the staged rows those planes read stay in its L2.
+template <int N, typename T>
+__global__ void __launch_bounds__(256)
+    k_stepd_gather(const cx<T>* __restrict__ Tz, int Np, const CellRec* __restrict__ cells,
+                   const int* __restrict__ ent, const T* __restrict__ wts, const T* __restrict__ cnt_inv,
+                   cx<T>* __restrict__ plane, int nz) {
+  using C = cx<T>;
+  constexpr int H = N / 2, CBLK = N * N / 256;
+  const int L = blockIdx.x;
+  int zi, cb;
+  if (nz % 8 == 0) {
+    const int x = L % 8, k = L / 8;
+    zi = x * (nz / 8) + k / CBLK;
+    cb = k % CBLK;
+  } else {
+    zi = L / CBLK;
+    cb = L % CBLK;
+  }
+  const int cell = cb * 256 + threadIdx.x;
+  const int ky = cell / N, kx = cell % N;
+  const C* Tp = Tz + (size_t)zi * Np * H;   // this plane's rows of every angle
+  // (-1)^u S_n[z][u] from the packed row of angle n, without branches: S[u] = P[u] (u < N/2),
+  // conj P[N-u] (u > N/2), Re P[0] (u = 0), Im P[0] (u = N/2)
+  auto sample = [&](int e, int code) CPRA_INLINE -> C {
+    const int n = code / N, u = code % N;
+    const int j = u <= H ? (u == H ? 0 : u) : N - u;
+    const C p = Tp[(size_t)n * H + j];
+    T re = u == H ? p.y : p.x;
+    T im = (u == 0 || u == H) ? (T)0 : (u > H ? -p.y : p.y);
+    if (u & 1) { re = -re; im = -im; }
+    C s = mk<C>(re, im);
+    if (wts) s = cscale(s, wts[e]);      // bilinear insertion weight
+    return s;
+  };
+  const CellRec rec = cells[cell];
+  C v = rec.first >= 0 ? sample(rec.begin, rec.first) : mk<C>((T)0, (T)0);
+  int e = rec.begin + 1;
+  for (; e + 8 <= rec.end; e += 8) {
+    int cd[8];
+    C sv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) cd[q] = ent[e + q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sv[q] = sample(e + q, cd[q]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v = cadd(v, sv[q]);
+  }
+  for (; e < rec.end; ++e) v = cadd(v, sample(e, ent[e]));
+  T f;
+  if constexpr (std::is_same<T, float>::value) f = __int_as_float(rec.inv_bits);
+  else f = cnt_inv[cell];
+  if ((ky + kx) & 1) f = -f;
+  plane[(size_t)zi * N * N + cell] = cscale(v, f);
+}
+
+// Rows: inverse transform of the gathered Q_z[ky][:] along kx, in place in the plane buffer.
+// Block: RB rows x R1 threads; grid: (N / RB) * nz, planes of an XCD as in the gather.
 template <int N, typename T, int RB>
 __global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
-    k_stepd_rows(const cx<T>* __restrict__ Tz, int Np, const CellRec* __restrict__ cells,
-                 const int* __restrict__ ent, const T* __restrict__ wts, const T* __restrict__ cnt_inv,
-                 const cx<T>* __restrict__ tw, cx<T>* __restrict__ plane, int nz) {
+    k_stepd_rows(const cx<T>* __restrict__ tw, cx<T>* __restrict__ plane, int nz) {
   using C = cx<T>;
-  constexpr int R1 = StepdCfg<N>::R1, R2 = StepdCfg<N>::R2, Q = R2 / R1, H = N / 2;
+  constexpr int R1 = StepdCfg<N>::R1, R2 = StepdCfg<N>::R2, Q = R2 / R1;
   static_assert(R1 * R2 == N && Q >= 1 && R2 % R1 == 0, "step D decomposition");
   constexpr int LS = R1 + 1;
   __shared__ C lds[RB * R2 * LS];
   const int a = threadIdx.x % R1;
   const int r = threadIdx.x / R1;
-  // 1D grid of (N / RB) * nz workgroups.  The dispatcher deals consecutive workgroups round-robin
-  // to the 8 XCDs; the planes are split so that XCD x takes planes [x nz/8, (x+1) nz/8) whole,
-  // which keeps the rows z of all angles that those planes gather within one L2
   constexpr int KB = N / RB;
   const int L = blockIdx.x;
   int zi, kyb;
@@ -103,45 +147,16 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
     kyb = L % KB;
   }
   const int ky = kyb * RB + r;
-  const C* Tp = Tz + (size_t)zi * Np * H;   // this plane's rows of every angle
   C* L0 = lds + r * R2 * LS;
+  C* row = plane + ((size_t)zi * N + ky) * N;
   C v[R2];
-  auto sample = [&](int e, int code) CPRA_INLINE -> C {
-    const int n = code / N, u = code % N;
-    C s = spectrum_row_at<N, T>(Tp + (size_t)n * H, u);
-    if (u & 1) { s.x = -s.x; s.y = -s.y; }
-    if (wts) s = cscale(s, wts[e]);      // bilinear insertion weight
-    return s;
-  };
-  // the cells go in groups of G, each gathered in two dependent batches (the cell records, then
-  // the first entries' samples) so that the loads of different cells overlap; the further entries
-  // of the cells that have them follow in CSR order
-  constexpr int G = R2 < 8 ? R2 : 8;
 #pragma unroll
-  for (int g0 = 0; g0 < R2; g0 += G) {
-    CellRec rec[G];
-#pragma unroll
-    for (int i = 0; i < G; ++i) rec[i] = cells[ky * N + a + R1 * (g0 + i)];
-#pragma unroll
-    for (int i = 0; i < G; ++i)
-      v[g0 + i] = rec[i].first >= 0 ? sample(rec[i].begin, rec[i].first) : mk<C>((T)0, (T)0);
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      for (int e = rec[i].begin + 1; e < rec[i].end; ++e) v[g0 + i] = cadd(v[g0 + i], sample(e, ent[e]));
-      const int kx = a + R1 * (g0 + i);
-      T f;
-      if constexpr (std::is_same<T, float>::value) f = __int_as_float(rec[i].inv_bits);
-      else f = cnt_inv[ky * N + kx];
-      if ((ky + kx) & 1) f = -f;
-      v[g0 + i] = cscale(v[g0 + i], f);
-    }
-  }
+  for (int b = 0; b < R2; ++b) v[b] = row[a + R1 * b];
   // inverse four-step along kx = a + R1 b -> x = c + R2 d
   dft<R2, +1>(v);
 #pragma unroll
   for (int c = 0; c < R2; ++c) L0[c * LS + a] = (c == 0 || a == 0) ? v[c] : cmulc(v[c], tw[wrapN<N>(a * c)]);
   __syncthreads();
-  C* out = plane + ((size_t)zi * N + ky) * N;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int c = a + R1 * q;
@@ -150,7 +165,7 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* RB)
     for (int ap = 0; ap < R1; ++ap) u[ap] = L0[c * LS + ap];
     dft<R1, +1>(u);
 #pragma unroll
-    for (int d = 0; d < R1; ++d) out[c + R2 * d] = u[d];
+    for (int d = 0; d < R1; ++d) row[c + R2 * d] = u[d];
   }
 }
 
@@ -201,7 +216,8 @@ void stepd_run(const cx<T>* P, int Np, cx<T>* Tz, const CellRec* cells, const in
   for (int z0 = 0; z0 < N; z0 += zc) {
     const int nz = (N - z0) < zc ? (N - z0) : zc;
     k_stepd_stage<N, T><<<dim3(nz, Np), 256, 0, st>>>(P, Tz, z0, Np);
-    k_stepd_rows<N, T, RB><<<(N / RB) * nz, R1 * RB, 0, st>>>(Tz, Np, cells, ent, wts, cnt_inv, tw, plane, nz);
+    k_stepd_gather<N, T><<<(N * N / 256) * nz, 256, 0, st>>>(Tz, Np, cells, ent, wts, cnt_inv, plane, nz);
+    k_stepd_rows<N, T, RB><<<(N / RB) * nz, R1 * RB, 0, st>>>(tw, plane, nz);
     k_stepd_cols<N, T, CC><<<dim3(N / CC, nz), R1 * CC, 0, st>>>(plane, tw, vol, z0);
   }
 }

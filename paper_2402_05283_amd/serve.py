@@ -15,7 +15,11 @@ episodes.  All scans with credit advance together, one episode per round, throug
 cpra_iterate_batch (scans of one size share launches, size classes overlap on their streams); frames
 are submitted without waiting for the GPU (the data check completes in stream order); at most
 `depth` episodes per scan are in flight, which bounds how long a frame submission can wait; a
-scan whose last frame has landed may queue up to `depth_final` and is issued first.
+scan whose last frame has landed (its latency clock is running) may queue up to `depth_final` and
+is issued first, and with `hold_others` the other scans issue no new episode while such a scan is
+unfinished, so it does not share the GPU with work whose latency is not yet being measured (the
+others fall behind their frames for that while and catch up afterwards; the logical schedule keeps
+their results unchanged).
 """
 from __future__ import annotations
 
@@ -40,6 +44,8 @@ class Scan:
         self.iters_done = 0
         self.in_flight = collections.deque()   # completion events of issued episodes
         self.t_last_frame = None
+        # host clock at: the last frame's submit, the last episode's issue, step D's issue
+        self.t_last_submit = self.t_last_issue = self.t_assemble = None
         self.volume = None
         self.volume_event = None
         self.t_done = None
@@ -60,14 +66,16 @@ class Server:
     algo, beta: the iteration (HIO with feedback beta, or ER).
     """
 
-    def __init__(self, hbm_budget, n_ei=10, r_frame=None, r_final=50, algo=_lib.HIO, beta=0.9, depth=2,
-                 depth_final=8, clock=time.perf_counter, plan_factory=None, batch_fn=None, stream_ctx=None):
+    def __init__(self, hbm_budget, n_ei=10, r_frame=None, r_final=50, algo=_lib.HIO, beta=0.9, depth=1,
+                 depth_final=8, hold_others=True, clock=time.perf_counter, plan_factory=None, batch_fn=None,
+                 stream_ctx=None):
         r_frame = n_ei if r_frame is None else r_frame
         if r_frame % n_ei or r_final % n_ei or r_frame <= 0 or r_final < 0:
             raise ValueError("r_frame and r_final must be non-negative multiples of n_ei (r_frame > 0)")
         self.budget, self.used = int(hbm_budget), 0
         self.n_ei, self.r_frame, self.r_final = n_ei, r_frame, r_final
         self.algo, self.beta, self.depth, self.depth_final = algo, beta, depth, max(depth, depth_final)
+        self.hold_others = hold_others
         self.clock = clock
         self.plan_factory = plan_factory or self._make_plan
         self.batch_fn = batch_fn or (lambda plans, n: _lib.iterate_batch(plans, n, self.algo, self.beta))
@@ -77,6 +85,8 @@ class Server:
         self.active = []
         self.finished = []
         self._next_id = 0
+        self.step_max_s = 0.0      # longest single scheduling round (host time)
+        self.slow_steps = 0        # rounds that took more than 50 ms
 
     # ---------------------------------------------------------------- set-up
     @staticmethod
@@ -130,6 +140,14 @@ class Server:
 
     def step(self):
         """One scheduling round.  Returns True if any work was issued or completed."""
+        t_in = self.clock()
+        progressed = self._step()
+        dt = self.clock() - t_in
+        self.step_max_s = max(self.step_max_s, dt)
+        self.slow_steps += dt > 0.05
+        return progressed
+
+    def _step(self):
         progressed = False
         for s in self.active:
             self._retire_events(s)
@@ -140,25 +158,37 @@ class Server:
                     s.plan.submit(n, I, S, asynchronous=True)
                 s.n_submitted += 1
                 s.credit += self.r_frame + (self.r_final if s.n_submitted == s.n_expected else 0)
+                if s.n_submitted == s.n_expected:
+                    s.t_last_submit = self.clock()
                 progressed = True
-        # a scan whose last frame is in may queue more episodes (its latency is being measured),
-        # and goes first in the batch
+        # a scan whose last frame has landed may queue more episodes (its latency is being
+        # measured) and goes first in the batch; with hold_others the rest wait for it
+        def timed(s):
+            return s.t_last_frame is not None
+
+        hold = self.hold_others and any(timed(s) for s in self.active)
+
         def room(s):
-            return (self.depth_final if s.n_submitted == s.n_expected else self.depth) - len(s.in_flight)
+            if timed(s):
+                return self.depth_final - len(s.in_flight)
+            return 0 if hold else self.depth - len(s.in_flight)
         batch = [s for s in self.active if s.credit > 0 and room(s) > 0]
-        batch.sort(key=lambda s: s.n_submitted != s.n_expected)
+        batch.sort(key=lambda s: not timed(s))
         if batch:
             self.batch_fn([s.plan for s in batch], self.n_ei)
             for s in batch:
                 s.credit -= self.n_ei
                 s.iters_done += self.n_ei
                 s.in_flight.append(self._record(s))
+                if s.credit == 0 and s.n_submitted == s.n_expected:
+                    s.t_last_issue = self.clock()
             progressed = True
         for s in list(self.active):
             if s.volume_event is None and s.n_submitted == s.n_expected and s.credit == 0:
                 with self.stream_ctx(s.plan):
                     s.volume = s.plan.assemble_volume()
                 s.volume_event = self._record(s)
+                s.t_assemble = self.clock()
                 progressed = True
             if s.volume_event is not None and s.volume_event.query():
                 s.t_done = self.clock()

@@ -130,3 +130,35 @@ def test_rejects_bad_schedules_and_oversized_scans():
     srv = serve.Server(1024)
     with pytest.raises(ValueError):
         srv.open_scan(64, 4)
+
+
+def test_scans_on_the_clock_run_alone():
+    """While a scan whose last frame has landed is unfinished, the other scans issue no episode
+    (hold_others); without it they keep issuing.  Either way every scan's schedule is the same."""
+    def trace(hold):
+        clock = FakeClock()
+        log = []
+        srv = make_server(1 << 40, log, clock, n_ei=5, r_frame=5, r_final=20, hold_others=hold)
+        a = srv.open_scan(64, 2, seed=0)
+        b = srv.open_scan(64, 6, seed=1)
+        for n in range(2):
+            srv.push_frame(a, n, None, None, t=0.0)
+        for n in range(5):
+            srv.push_frame(b, n, None, None, t=0.0)
+        iters_of_b = []
+        while not a.done:
+            clock.t += 1e-3
+            srv.step()
+            iters_of_b.append(b.iters_done)
+        srv.push_frame(b, 5, None, None, t=clock.t)
+        while srv.busy():
+            clock.t += 1e-3
+            srv.step()
+        return log, iters_of_b, a, b
+    log_h, b_held, a_h, b_h = trace(True)
+    log_f, b_free, a_f, b_f = trace(False)
+    assert max(b_held) == 0
+    assert max(b_free) > 5
+    for sid in (0, 1):
+        assert ops_of(log_h, sid) == ops_of(log_f, sid)
+    assert a_h.volume == ("volume", 0, 2 * 5 + 20) and b_h.volume == ("volume", 1, 6 * 5 + 20)
