@@ -187,6 +187,7 @@ Layout layout_of(const cpra_params* p) {
   L.csr_ptr = take((N * N + 1) * 4);
   L.csr_cell = take(N * N * sizeof(cpra::CellRec));
   const size_t ents = Np * N * (p->insertion == CPRA_INSERT_BILINEAR ? 4 : 1);   // at most
+  L.csr_heavy = take((ents / (cpra::kStepdHeavy + 1) + 1) * sizeof(cpra::CellRec));
   L.csr_ent = take(ents * 4);
   L.csr_w = take(p->insertion == CPRA_INSERT_BILINEAR ? ents * rs : 0);
   L.cnt_inv = take(N * N * rs);
@@ -468,9 +469,9 @@ cpra_status cpra_plan_create(const cpra_params* params, void* workspace, size_t 
 
 // Step-D tables: the integer cell map of the Fourier-slice insertion (built on the host in FP64),
 // the bilinear weights, and the inverse count (or weight sum) per cell, packed into one pinned
-// image: row pointers, cell records, entries, weights, inverse counts, each 256-byte aligned.  The
-// image depends only on N, Np, the angles, the insertion and the precision, so a process keeps the
-// images of up to kStepdImages shapes and later plans of a shape upload the same image (scans of a
+// image: row pointers, cell records, entries, weights, inverse counts, heavy-cell records, each
+// 256-byte aligned.  The image depends only on N, Np, the angles, the insertion and the precision,
+// so a process keeps the images of up to kStepdImages shapes and later plans of a shape upload the same image (scans of a
 // serving mix repeat a few shapes).  Built at the first step-D call rather than at plan creation,
 // so that this host work overlaps the iterations already queued on the stream; the uploads come
 // from pinned memory, so they are ordered on the stream before step D's kernels without the host
@@ -482,7 +483,8 @@ struct StepdImage {
   std::vector<double> theta;
   void* host = nullptr;        // pinned
   size_t bytes = 0;
-  size_t piece[5] = {};        // bytes of each piece, in image order
+  size_t piece[6] = {};        // bytes of each piece, in image order
+  int n_heavy = 0;
 };
 constexpr size_t kStepdImages = 16;
 std::mutex g_img_mu;
@@ -509,28 +511,36 @@ std::shared_ptr<StepdImage> build_stepd_image(const cpra_params& p, const std::v
     inv_d[c] = tot > 0.0 ? 1.0 / tot : 0.0;
     inv_f[c] = (float)inv_d[c];
   }
-  // the cell records of step D's gather: first entry, entry range, inverse count as FP32 bits
-  std::vector<cpra::CellRec> cell(NN);
+  // the cell records of step D's gather: first entry, entry range, inverse count as FP32 bits; cells
+  // with more than kStepdHeavy entries go to the heavy list (record: first = the cell index) and are
+  // marked first = -2 in the gather's table
+  std::vector<cpra::CellRec> cell(NN), heavy;
   for (size_t c = 0; c < NN; ++c) {
     cpra::CellRec& r = cell[c];
     r.begin = rp[c];
     r.end = rp[c + 1];
     r.first = rp[c] < rp[c + 1] ? ent[rp[c]] : -1;
     std::memcpy(&r.inv_bits, &inv_f[c], 4);
+    if (r.end - r.begin > cpra::kStepdHeavy) {
+      heavy.push_back(cpra::CellRec{(int)c, r.begin, r.end, r.inv_bits});
+      r.first = -2;
+    }
   }
-  const void* src[5] = {rp.data(), cell.data(), ent.data(),
+  img->n_heavy = (int)heavy.size();
+  const void* src[6] = {rp.data(), cell.data(), ent.data(),
                         img->f64 ? (const void*)wts.data() : (const void*)wf.data(),
-                        img->f64 ? (const void*)inv_d.data() : (const void*)inv_f.data()};
+                        img->f64 ? (const void*)inv_d.data() : (const void*)inv_f.data(), heavy.data()};
   img->piece[0] = rp.size() * 4;
   img->piece[1] = NN * sizeof(cpra::CellRec);
   img->piece[2] = ent.size() * 4;
   img->piece[3] = img->bil ? wts.size() * (img->f64 ? 8 : 4) : 0;
   img->piece[4] = NN * (img->f64 ? 8 : 4);
+  img->piece[5] = heavy.size() * sizeof(cpra::CellRec);
   for (size_t b : img->piece) img->bytes += align_up(b);
   img->host = pinned_take(img->bytes);
   if (!img->host) return nullptr;
   char* hb = static_cast<char*>(img->host);
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < 6; ++i) {
     if (img->piece[i]) std::memcpy(hb, src[i], img->piece[i]);
     hb += align_up(img->piece[i]);
   }
@@ -562,14 +572,17 @@ static cpra_status ensure_stepd_tables(cpra_plan_t pl) {
     img = built;
   }
   const Layout& L = pl->L;
-  const size_t dst[5] = {L.csr_ptr, L.csr_cell, L.csr_ent, L.csr_w, L.cnt_inv};
+  if (img->piece[5] > L.csr_ent - L.csr_heavy)   // cannot happen: each heavy cell holds > kStepdHeavy entries
+    return fail(pl, CPRA_ERR_DEVICE, "step D: %d heavy cells exceed their table", img->n_heavy);
+  const size_t dst[6] = {L.csr_ptr, L.csr_cell, L.csr_ent, L.csr_w, L.cnt_inv, L.csr_heavy};
   HIPCHK(pl, hipEventCreateWithFlags(&pl->ev_stepd, hipEventDisableTiming));
   const char* hb = static_cast<const char*>(img->host);
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < 6; ++i) {
     if (img->piece[i])
       HIPCHK(pl, hipMemcpyAsync(pl->ws + dst[i], hb, img->piece[i], hipMemcpyHostToDevice, pl->stream));
     hb += align_up(img->piece[i]);
   }
+  pl->n_heavy = img->n_heavy;
   HIPCHK(pl, hipEventRecord(pl->ev_stepd, pl->stream));
   pl->stepd_ready = true;
   return CPRA_OK;

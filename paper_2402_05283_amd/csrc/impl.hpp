@@ -19,7 +19,7 @@ namespace cpra_impl {
 
 struct Layout {
   size_t P, Pmid, Pc, g0, g1, A2, ampscale, maskw, den, tw, coup, alist, iota, errpart, errhist, flags, stage_I,
-      stage_S, csr_ptr, csr_cell, csr_ent, csr_w, cnt_inv, plane, stage_T, prep_part, mtab, swk, ctab, total;
+      stage_S, csr_ptr, csr_cell, csr_heavy, csr_ent, csr_w, cnt_inv, plane, stage_T, prep_part, mtab, swk, ctab, total;
   int zc;   // z-planes per step-D chunk
 };
 
@@ -75,6 +75,7 @@ struct cpra_plan_s {
   // process caches per shape (ev_stepd: the uploads have completed); h_stepd holds the plan's own
   // image when the cache was full
   bool stepd_ready = false;
+  int n_heavy = 0;             // step-D cells summed by a wavefront each
   void* h_stepd = nullptr;
   size_t stepd_bytes = 0;
   hipEvent_t ev_stepd = nullptr;
@@ -398,7 +399,7 @@ struct Impl {
   }
   static void assemble(cpra_plan_t pl, void* vol) {
     stepd_run<N, T>(at<C>(pl, pl->L.P), pl->p.Np, at<C>(pl, pl->L.stage_T), at<CellRec>(pl, pl->L.csr_cell),
-                    at<int>(pl, pl->L.csr_ent),
+                    at<CellRec>(pl, pl->L.csr_heavy), pl->n_heavy, at<int>(pl, pl->L.csr_ent),
                     pl->p.insertion == CPRA_INSERT_BILINEAR ? at<T>(pl, pl->L.csr_w) : nullptr,
                     at<T>(pl, pl->L.cnt_inv), at<C>(pl, pl->L.tw), at<C>(pl, pl->L.plane), pl->L.zc,
                     reinterpret_cast<T*>(vol), pl->stream);

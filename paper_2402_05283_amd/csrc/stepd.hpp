@@ -63,6 +63,13 @@ struct CellRec {
   int first, begin, end, inv_bits;
 };
 
+// Cells with more than kStepdHeavy entries (the cells near k = 0: the zero-frequency cell holds one
+// entry per angle) are left out of the per-cell gather, whose time is set by its longest chain of
+// dependent loads, and summed by k_stepd_heavy, one wavefront per (cell, plane).  Their records
+// carry first = -2 and an empty range; the heavy list holds their real records with first = the
+// cell index.
+constexpr int kStepdHeavy = 16;
+
 // Gather: Q_z[ky][kx] = (-1)^(ky+kx) / cnt(ky,kx) * sum over the cell's entries (n, u) of
 // (-1)^u S_n[z][u] (bilinear: weighted), one thread per cell, into the plane buffer.  No LDS, so
 // many waves are resident to hide the dependent loads.  A cell's entries are summed in CSR order,
@@ -103,6 +110,7 @@ __global__ void __launch_bounds__(256)
     return s;
   };
   const CellRec rec = cells[cell];
+  if (rec.first == -2) return;          // summed by k_stepd_heavy
   C v = rec.first >= 0 ? sample(rec.begin, rec.first) : mk<C>((T)0, (T)0);
   int e = rec.begin + 1;
   for (; e + 8 <= rec.end; e += 8) {
@@ -121,6 +129,55 @@ __global__ void __launch_bounds__(256)
   else f = cnt_inv[cell];
   if ((ky + kx) & 1) f = -f;
   plane[(size_t)zi * N * N + cell] = cscale(v, f);
+}
+
+// The heavy cells of the gather: one wavefront per (heavy cell, plane), lane l summing entries
+// begin + l, begin + l + 64, ... in order, then a butterfly sum over the 64 lanes.  grid
+// (n_heavy / 4 rounded up, nz), 4 wavefronts per workgroup.
+template <int N, typename T>
+__global__ void __launch_bounds__(256)
+    k_stepd_heavy(const cx<T>* __restrict__ Tz, int Np, const CellRec* __restrict__ heavy, int n_heavy,
+                  const int* __restrict__ ent, const T* __restrict__ wts, const T* __restrict__ cnt_inv,
+                  cx<T>* __restrict__ plane) {
+  using C = cx<T>;
+  constexpr int H = N / 2;
+  const int h = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  const int zi = blockIdx.y;
+  if (h >= n_heavy) return;             // whole wavefronts leave together
+  const CellRec rec = heavy[h];
+  const int cell = rec.first;
+  const C* Tp = Tz + (size_t)zi * Np * H;
+  T re = 0, im = 0;
+  for (int e = rec.begin + lane; e < rec.end; e += 64) {
+    const int code = ent[e];
+    const int n = code / N, u = code % N;
+    const int j = u <= H ? (u == H ? 0 : u) : N - u;
+    const C p = Tp[(size_t)n * H + j];
+    T sr = u == H ? p.y : p.x;
+    T si = (u == 0 || u == H) ? (T)0 : (u > H ? -p.y : p.y);
+    if (u & 1) { sr = -sr; si = -si; }
+    if (wts) {
+      const T w = wts[e];
+      sr *= w;
+      si *= w;
+    }
+    re += sr;
+    im += si;
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    re += __shfl_xor(re, m);
+    im += __shfl_xor(im, m);
+  }
+  if (lane == 0) {
+    const int ky = cell / N, kx = cell % N;
+    T f;
+    if constexpr (std::is_same<T, float>::value) f = __int_as_float(rec.inv_bits);
+    else f = cnt_inv[cell];
+    if ((ky + kx) & 1) f = -f;
+    plane[(size_t)zi * N * N + cell] = mk<C>(re * f, im * f);
+  }
 }
 
 // Rows: inverse transform of the gathered Q_z[ky][:] along kx, in place in the plane buffer.
@@ -207,8 +264,9 @@ __global__ void __launch_bounds__(StepdCfg<N>::R1* CC)
 
 // tw: W_N^j, j < N (the first N entries of the plan's twiddle table)
 template <int N, typename T>
-void stepd_run(const cx<T>* P, int Np, cx<T>* Tz, const CellRec* cells, const int* ent, const T* wts,
-               const T* cnt_inv, const cx<T>* tw, cx<T>* plane, int zc, T* vol, hipStream_t st) {
+void stepd_run(const cx<T>* P, int Np, cx<T>* Tz, const CellRec* cells, const CellRec* heavy, int n_heavy,
+               const int* ent, const T* wts, const T* cnt_inv, const cx<T>* tw, cx<T>* plane, int zc, T* vol,
+               hipStream_t st) {
   constexpr int R1 = StepdCfg<N>::R1, R2 = StepdCfg<N>::R2;
   // rows / columns per workgroup: up to 256 threads, LDS within 128 KiB
   constexpr int RB = stepd_lines<N, T>(256 / R1 < N ? 256 / R1 : N, (size_t)R2 * (R1 + 1));
@@ -217,6 +275,9 @@ void stepd_run(const cx<T>* P, int Np, cx<T>* Tz, const CellRec* cells, const in
     const int nz = (N - z0) < zc ? (N - z0) : zc;
     k_stepd_stage<N, T><<<dim3(nz, Np), 256, 0, st>>>(P, Tz, z0, Np);
     k_stepd_gather<N, T><<<(N * N / 256) * nz, 256, 0, st>>>(Tz, Np, cells, ent, wts, cnt_inv, plane, nz);
+    if (n_heavy > 0)
+      k_stepd_heavy<N, T><<<dim3((n_heavy + 3) / 4, nz), 256, 0, st>>>(Tz, Np, heavy, n_heavy, ent, wts, cnt_inv,
+                                                                        plane);
     k_stepd_rows<N, T, RB><<<(N / RB) * nz, R1 * RB, 0, st>>>(tw, plane, nz);
     k_stepd_cols<N, T, CC><<<dim3(N / CC, nz), R1 * CC, 0, st>>>(plane, tw, vol, z0);
   }
