@@ -130,12 +130,19 @@ print(json.dumps({{"iter_s": t1 - t0}}))
 
 
 def kernel_source_hash():
-    """SHA-256 over the sources that define the column and row passes and their launches."""
+    """SHA-256 over the sources that define the column and row passes and their launches: cx.hpp,
+    kernels.hpp and the iteration's launch function in impl.hpp (from `static void step(` to the
+    next function)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("cx.hpp", "kernels.hpp", "impl.hpp"):
+    for f in ("cx.hpp", "kernels.hpp"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(CSRC, "impl.hpp")) as fh:
+        src = fh.read()
+    a = src.index("  static void step(")
+    b = src.index("  static void colerr(", a)
+    h.update(src[a:b].encode())
     return h.hexdigest()
 
 
@@ -802,7 +809,7 @@ def main():
     if args.summarize_trace:
         cmd = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace -o run "
                "-- python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-compare --guesses 0 --serve-scans 0 --batch-scans 0 "
-               "> gpurun_out/trace_bench.json")
+               "--no-autotune > gpurun_out/trace_bench.json")
         print(summarize_trace(*args.summarize_trace, cmd), end="")
         return
     if args.summarize_sq:
@@ -814,7 +821,8 @@ def main():
         return
     if args.summarize_pmc:
         cmd = ("timeout -s KILL 120 rocprofv3 --pmc {counter} --output-format csv -d gpurun_out/{out} -o run "
-               "-- python3 bench.py --steps 1 --warmup 0 --iters 20 --no-cpu-baseline --serve-scans 0 --calibrate-copy")
+               "-- python3 bench.py --steps 1 --warmup 0 --iters 20 --no-cpu-baseline --serve-scans 0 --no-compare "
+               "--guesses 0 --batch-scans 0 --no-autotune --calibrate-copy")
         print(summarize_pmc(*args.summarize_pmc, cmd), end="")
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
