@@ -289,7 +289,9 @@ def summarize_trace(trace_dir, bench_json, cmd):
              "Command (repo root, one MI355X):", "", f"    {cmd}", "",
              f"Each step: plan set-up, submit of 360 angles (prep + initial objects), {b['config']['iterations']} "
              f"HIO iterations (coupling every {b['config']['n_ei']}), step D into a 512^3 volume.  "
-             f"Only the headline legs run (no comparison, schedule, batch or serving legs).  "
+             f"Besides the headline, only the FP16-amplitude leg (the `__half2` column passes) and the "
+             f"error-history leg run (no comparison, schedule, batch or serving legs); the row pass is the "
+             f"same kernel for both amplitude types.  "
              f"bench.py in the same run: value {b['value']:.0f} pattern-iterations/s, {b['ms_per_step']:.1f} ms "
              f"per step; HIP-event mean launch time k_col {ev.get('k_col', 0) * 1e3:.1f} us, "
              f"k_row {ev.get('k_row', 0) * 1e3:.1f} us.", "",
@@ -905,26 +907,32 @@ def main():
     ms_per_step = total / args.steps * 1e3
     value = args.iters * NP * args.steps / total
 
-    col_b, row_b = algorithmic_bytes(N, NP, N_EI, amp_bytes=4 if args.amp16 else 8)
+    # per-launch figures: a launch covers all 360 angles, or a chunk of them when the tuning chose
+    # chunk-major order (then each pass takes several launches per iteration)
+    col_b360, row_b360 = algorithmic_bytes(N, NP, N_EI, amp_bytes=4 if args.amp16 else 8)
+    n_it = args.iters * args.steps
+    per_launch = n_it / max(col_n, 1)          # fraction of the 360 angles one launch covers
+    col_b, row_b = col_b360 * per_launch, row_b360 * per_launch
     col_avg = col_ms / max(col_n, 1)
     row_avg = row_ms / max(row_n, 1)
     col_gbs = col_b / (col_avg * 1e-3) / 1e9
     row_gbs = row_b / (row_avg * 1e-3) / 1e9
     dom = ("k_col", col_avg, col_gbs, col_b) if col_avg >= row_avg else ("k_row", row_avg, row_gbs, row_b)
     tr = load_traffic() if not args.amp16 else None
-    traffic = round(tr[dom[0]]["traffic_bytes"]) if tr else None
-    iter_ms = (col_ms + row_ms) / max(col_n, 1)
-    it_gbs = (col_b + row_b) / (iter_ms * 1e-3) / 1e9
+    traffic = round(tr[dom[0]]["traffic_bytes"] * per_launch) if tr else None
+    iter_ms = (col_ms + row_ms) / max(n_it, 1)
+    it_gbs = (col_b360 + row_b360) / (iter_ms * 1e-3) / 1e9
     full_b = 46.525 * N * N * NP                # full-complex-spectrum byte model (two complex planes per pass)
     roofline = {"bound": "hbm", "achieved": round(dom[2], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom[2] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom[0],
                 "avg_launch_ms": round(dom[1], 5), "bytes_per_launch": int(dom[3]),
+                "launches_per_iteration": round(1.0 / per_launch, 3),
                 "other": {"kernel": "k_row" if dom[0] == "k_col" else "k_col",
                           "avg_launch_ms": round(row_avg if dom[0] == "k_col" else col_avg, 5),
                           "achieved": round(row_gbs if dom[0] == "k_col" else col_gbs, 1),
                           "frac": round((row_gbs if dom[0] == "k_col" else col_gbs) / HBM_PEAK_GBS, 4)},
                 "fused_iteration": {"achieved": round(it_gbs, 1), "frac": round(it_gbs / HBM_PEAK_GBS, 4),
-                                    "bytes": int(col_b + row_b), "ms": round(iter_ms, 5),
+                                    "bytes": int(col_b360 + row_b360), "ms": round(iter_ms, 5),
                                     "what": "column + row pass algorithmic bytes over their summed mean "
                                             "launch times: the whole fused FFT + projection iteration"},
                 "full_complex_model_frac": round(full_b / (iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}

@@ -276,9 +276,11 @@ cpra_status cpra_set_tuning(cpra_plan_t plan, const cpra_tuning* t);
  * HIO iterations (rounded up to whole episodes) for every combination of
  * row_tile {0, 1}, chunk {0, slots/2, slots/4 where >= 16 slots} and graphs
  * {0, 1}, each after one warm episode, with HIP events on `hip_stream`.
- * Returns the fastest in *best and records it for the shape (N, Np, real
- * type, amplitude type, guesses): plans of that shape created afterwards in
- * this process start with these choices.  Synchronises the stream.
+ * Returns the fastest in *best, or the default choices (all 0) unless the
+ * fastest beats them by more than 2% (closer than that is timing noise), and
+ * records it for the shape (N, Np, real type, amplitude type, guesses): plans
+ * of that shape created afterwards in this process start with these choices.
+ * Synchronises the stream.
  */
 cpra_status cpra_autotune(const cpra_params* params, void* workspace, size_t workspace_bytes, void* hip_stream,
                           int32_t n_iter, cpra_tuning* best);

@@ -830,6 +830,8 @@ cpra_status cpra_set_tuning(cpra_plan_t pl, const cpra_tuning* t) {
   return CPRA_OK;
 }
 
+constexpr double kTuneMargin = 0.02;
+
 cpra_status cpra_autotune(const cpra_params* params, void* workspace, size_t workspace_bytes, void* hip_stream,
                           int32_t n_iter, cpra_tuning* best) {
   if (!best) return fail(nullptr, CPRA_ERR_ARG, "best is NULL");
@@ -874,7 +876,7 @@ cpra_status cpra_autotune(const cpra_params* params, void* workspace, size_t wor
   std::vector<int> chunks = {0};
   for (int d : {2, 4})
     if (S / d >= 16) chunks.push_back((S + d - 1) / d);
-  cpra_tuning top{};
+  cpra_tuning top{}, dflt{};
   top.ms_per_iteration = -1.0;
   for (int rt = 0; rt < 2; ++rt)
     for (int ch : chunks)
@@ -892,11 +894,17 @@ cpra_status cpra_autotune(const cpra_params* params, void* workspace, size_t wor
         float ms = 0.f;
         HIPCHK(pl, hipEventElapsedTime(&ms, e0, e1));
         const double per = (double)ms / iters;
+        if (rt == 0 && ch == 0 && gr == 0) {
+          dflt = cand;
+          dflt.ms_per_iteration = per;
+        }
         if (top.ms_per_iteration < 0.0 || per < top.ms_per_iteration) {
           top = cand;
           top.ms_per_iteration = per;
         }
       }
+  // a choice within kTuneMargin of the default's time is noise: keep the default
+  if (top.ms_per_iteration > dflt.ms_per_iteration * (1.0 - kTuneMargin)) top = dflt;
   *best = top;
   const TuneKey key{params->N, params->Np, params->real_type, params->amp_type, pl->R};
   std::lock_guard<std::mutex> lk(g_tune_mu);
