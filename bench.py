@@ -237,7 +237,8 @@ def summarize_sq(sq_dir, cmd):
     import re
     acc = {}
     for r in _pmc_rows(sq_dir):
-        m = re.search(r"cpra::(k_col_pair|k_row|k_stepd_rows|k_stepd_cols)<512, float[^(]*?(?:, (true|false))?[,>]",
+        m = re.search(r"cpra::(k_col_pair|k_row|k_stepd_stage|k_stepd_gather|k_stepd_heavy|k_stepd_rows|k_stepd_cols)"
+                      r"<512, float[^(]*?(?:, (true|false))?[,>]",
                       r["Kernel_Name"])
         if not m:
             continue
@@ -256,7 +257,7 @@ def summarize_sq(sq_dir, cmd):
              "VALU busy = VALU instructions x 4 cycles / (1024 SIMDs x launch cycles).", "",
              "| Kernel | Launches | Waves | VALU instr / wave | Dependency waits / wave time | VALU issue / wave time | "
              "Waves resident per CU | VALU busy |", "|---|---|---|---|---|---|---|---|"]
-    for k in ("k_col_pair", "k_row", "k_stepd_rows", "k_stepd_cols"):
+    for k in ("k_col_pair", "k_row", "k_stepd_stage", "k_stepd_gather", "k_stepd_heavy", "k_stepd_rows", "k_stepd_cols"):
         a = acc.get(k)
         if not a:
             continue

@@ -185,7 +185,7 @@ struct Impl {
     using CG = ColGeom<N>;
     using RG = RowGeom<N>;
     dim3 gc(CG::TILES, count), bc(CG::R1 * CG::C);
-    if constexpr (CG::S == 2)
+    if constexpr (CG::S >= 2)
       k_col_pair<N, T, AP, 1, false><<<gc, bc, 0, pl->stream>>>(
           nullptr, at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2), at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw),
           d_list, nullptr, pl->p.Np, nullptr, CG::TILES, pl->p.seed);
@@ -220,7 +220,7 @@ struct Impl {
                                       at<T>(pl, pl->L.ampscale), at<C>(pl, pl->L.tw), al, cp, pl->p.Np, ep,
                                       CG::TILES, 0);
     };
-    if constexpr (CG::S == 2) {
+    if constexpr (CG::S >= 2) {
       if (couple) {
         if (errpart) launch(k_col_pair<N, T, AP, 0, true, true>, errpart);
         else launch(k_col_pair<N, T, AP, 0, false, true>, nullptr);
@@ -263,7 +263,7 @@ struct Impl {
     using CG = ColGeom<N>;
     dim3 gc(CG::TILES, nact), bc(CG::R1 * CG::C);
     auto kern = [&]() {
-      if constexpr (CG::S == 2) return k_col_pair<N, T, AP, 0, true, false>;
+      if constexpr (CG::S >= 2) return k_col_pair<N, T, AP, 0, true, false>;
       else return k_col<N, T, AP, 0, true, false>;
     }();
     kern<<<gc, bc, 0, pl->stream>>>(at<C>(pl, pl->L.P), at<C>(pl, pl->L.Pmid), at<AP>(pl, pl->L.A2),
@@ -373,7 +373,7 @@ struct Impl {
       ft.start[bn] = tot;
       if (tot == 0) continue;
       dim3 gc(CG::TILES, tot), bc(CG::R1 * CG::C);
-      if constexpr (CG::S == 2) {
+      if constexpr (CG::S >= 2) {
         if (couple) k_colpair_fused<N, T, AP, true><<<gc, bc, 0, st>>>(ft);
         else k_colpair_fused<N, T, AP, false><<<gc, bc, 0, st>>>(ft);
       } else {

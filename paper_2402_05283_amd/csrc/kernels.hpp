@@ -38,7 +38,10 @@ template <> struct ColCfg<256> { static constexpr int R1 = 16, R2 = 16, C = 16, 
 template <> struct ColCfg<192> { static constexpr int R1 = 8, R2 = 24, C = 16, S = 1; };
 template <> struct ColCfg<384> { static constexpr int R1 = 8, R2 = 48, C = 16, S = 1; };
 template <> struct ColCfg<512> { static constexpr int R1 = 32, R2 = 16, C = 8, S = 2; };
-template <> struct ColCfg<1024> { static constexpr int R1 = 32, R2 = 32, C = 8, S = 1; };
+#ifndef CPRA_C1024
+#define CPRA_C1024 8
+#endif
+template <> struct ColCfg<1024> { static constexpr int R1 = 64, R2 = 16, C = CPRA_C1024, S = 4; };
 
 // Row half-spectrum transform of length L = N/2 = F1 * F2 (F1: frequency
 // residue modulus, F2: space residue modulus).  T = F1 threads per row:
@@ -82,7 +85,7 @@ template <int N> struct ColGeom {
   static constexpr int PADC = (S == 1) ? 1 : 16;   // paired layout: slab stride = 16 mod 32 slots
   static constexpr int TILES = (N / 2) / C;
   static_assert(R1 * R2 == N && (N / 2) % C == 0, "column decomposition");
-  static_assert(S == 1 ? (R2 % R1 == 0) : (S == 2 && R1 / 2 == R2), "step-2 ownership");
+  static_assert(S == 1 ? (R2 % R1 == 0) : ((S == 2 || S == 4) && R1 == S * R2), "step-2 ownership");
 };
 
 // x mod N into [0, N) (a mask for powers of two; sizes with a factor 3 take the remainder)
@@ -105,6 +108,10 @@ template <int N> __host__ __device__ __forceinline__ int wrapN(int x) {
 #endif
 template <int N> struct PixCfg { static constexpr int CB = ColCfg<N>::C; };
 template <> struct PixCfg<512> { static constexpr int CB = CPRA_PIX512; };
+#ifndef CPRA_PIX1024
+#define CPRA_PIX1024 8
+#endif
+template <> struct PixCfg<1024> { static constexpr int CB = CPRA_PIX1024; };
 template <int N> __host__ __device__ __forceinline__ size_t pix(int z, int j) {
   constexpr int CB = PixCfg<N>::CB;
   return ((size_t)(j / CB) * N + z) * CB + (j % CB);
@@ -299,9 +306,10 @@ __global__ void k_twiddles(cx<T>* tw) {
   } else if (i < TL::COLI) {
     const int r = i - TL::COLF; e = (long)(r / R2) * (r % R2);
   } else if (i < TL::RC2R) {
-    // coli [c][a-slot]: a = slot (S = 1) or a = s + 2 a' with slot = s R1/2 + a' (S = 2)
+    // coli [c][a-slot]: a = slot (S = 1) or a = s + S a' with slot = s R1/S + a' (S = 2, 4)
+    constexpr int S = ColCfg<N>::S;
     const int r = i - TL::COLI, c = r / R1, slot = r % R1;
-    const int aa = (ColCfg<N>::S == 1) ? slot : (slot / (R1 / 2)) + 2 * (slot % (R1 / 2));
+    const int aa = (S == 1) ? slot : (slot / (R1 / S)) + S * (slot % (R1 / S));
     e = (long)c * aa; cj = true;
   } else if (i < TL::RR2C) {
     const int r = i - TL::RC2R; e = 2L * (r / F2) * (r % F2); cj = true;
@@ -729,12 +737,15 @@ __global__ void __launch_bounds__(ColCfg<N>::R1* ColCfg<N>::C)
                                      ERR ? errpart + (size_t)ai * ntiles + blockIdx.x : nullptr, seed);
 }
 
-// Column pass with paired step-2 DFTs (S = 2): R1 = 2 R2 threads per column,
-// R2 values each.  Step 1 as in k_col; in step 2 thread a owns c = a/2 and
-// half s = a%2 of the R1-point DFT over a: an R2-point DFT over the a of its
-// parity, a W_R1^{s k'} twiddle and a radix-2 butterfly with its partner
-// lane (a ^ 1, i.e. lane ^ C).  It then holds G[w] for w = c + R2 (k' + R2 s).
-// The inverse mirrors it.  Same modes and outputs as k_col.
+// Column pass with step-2 DFTs shared by S = 2 or 4 lanes: R1 = S R2 threads per
+// column, R2 values each.  Step 1 as in k_col; in step 2 thread a owns c = a/S and
+// part s = a%S of the R1-point DFT over a: an R2-point DFT over the a = s (mod S),
+// a W_R1^{s k'} twiddle and an S-point DFT across the S lanes of c.  S = 2: one
+// radix-2 butterfly with lane a ^ 1 (lane ^ C); it then holds G[w] for
+// w = c + R2 (k' + R2 s).  S = 4: a radix-2 butterfly across s1 (lane ^ 2C), then
+// one across s0 (lane ^ C) with W_4^{s1} on the odd half, s = s0 + 2 s1; it then
+// holds G[w] for w = c + R2 (k' + R2 m), m = s1 + 2 s0.  The inverse mirrors it.
+// Same modes and outputs as k_col.
 // value of lane ^ PM (the step-2 partner)
 template <int PM, typename T>
 __device__ __forceinline__ cx<T> pair_lane(cx<T> v) {
@@ -750,18 +761,25 @@ __device__ __forceinline__ void col_pair_body(const cx<T>* __restrict__ P, cx<T>
   using Gm = ColGeom<N>;
   using TL = TwLayout<N>;
   using C = cx<T>;
-  constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::C, H = N / 2, NT = R1 * CC;
+  constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::C, H = N / 2, NT = R1 * CC, SS = Gm::S;
   constexpr int LSTRIDE = R1 * CC + Gm::PADC;
-  static_assert(Gm::S == 2, "paired kernel");
+  static_assert(SS == 2 || SS == 4, "step 2 shared by 2 or 4 lanes");
   __shared__ C lds[R2 * LSTRIDE];
-  __shared__ C zl[(MODE == 0) ? N : 1];
+  // tile 0's column exchange: its own array (S = 2), or lds (S = 4, so that four workgroups fit a
+  // CU): written after every step-2 read of lds (barrier), read before the inverse writes to lds
+  // (barrier)
+  __shared__ C zl_own[(MODE == 0 && SS == 2) ? N : 1];
+  static_assert(R2 * LSTRIDE >= N, "column exchange fits in lds");
+  C* const zl = SS == 2 ? zl_own : lds;
   // lane = a * CC + col: the lanes of one row of a tile are neighbours, and the
-  // step-2 partner (a ^ 1) is lane ^ CC
+  // step-2 partners (a ^ 1, a ^ 2) are lane ^ CC, lane ^ 2 CC
   constexpr int PM = CC;
   const int col = threadIdx.x % CC;
   const int a = threadIdx.x / CC;          // row residue in step 1
-  const int sh = a & 1;
-  const int c = a >> 1;                    // step 2: owned c and half sh
+  const int sh = a & (SS - 1);             // step 2: part s of the DFT over a ...
+  const int c = a / SS;                    // ... for the owned c
+  const int s0 = sh & 1, s1 = sh >> 1;
+  const int mo = SS == 2 ? sh : s1 + 2 * s0;   // output quarter / half: G[c + R2 (k' + R2 mo)]
   const int tile = blockIdx.x;
   const int j0 = col_tile_start<N>(tile);
   const int j = j0 + col;
@@ -815,22 +833,36 @@ __device__ __forceinline__ void col_pair_body(const cx<T>* __restrict__ P, cx<T>
     if (j0 != 0) {
       sfor<0, R2>([&](auto kv) CPRA_INLINE {
         constexpr int k = decltype(kv)::value;
-        amp[k] = AmpIO<AP>::raw(An + pix<N>(c + R2 * (k + R2 * sh), j));
+        amp[k] = AmpIO<AP>::raw(An + pix<N>(c + R2 * (k + R2 * mo), j));
       });
     }
-    // forward step 2: half sh of the R1-point DFT over a for this c
+    // forward step 2: part sh of the R1-point DFT over a for this c
     sfor<0, R2>([&](auto kv) CPRA_INLINE {
       constexpr int k = decltype(kv)::value;
-      g[k] = lds[c * LSTRIDE + (sh + 2 * k) * CC + col];
+      g[k] = lds[c * LSTRIDE + (sh + SS * k) * CC + col];
     });
     dft<R2, -1>(g);
-    const T sgn = sh ? (T)-1 : (T)1;
-    sfor<0, R2>([&](auto kv) CPRA_INLINE {
-      constexpr int k = decltype(kv)::value;
-      const C t = sh ? twc<-1, k, R1>(g[k]) : g[k];
-      const C o = pair_lane<PM, T>(t);
-      g[k] = mk<C>(o.x + sgn * t.x, o.y + sgn * t.y);    // sh = 0: t + o; sh = 1: o - t
-    });
+    if constexpr (SS == 2) {
+      const T sgn = sh ? (T)-1 : (T)1;
+      sfor<0, R2>([&](auto kv) CPRA_INLINE {
+        constexpr int k = decltype(kv)::value;
+        const C t = sh ? twc<-1, k, R1>(g[k]) : g[k];
+        const C o = pair_lane<PM, T>(t);
+        g[k] = mk<C>(o.x + sgn * t.x, o.y + sgn * t.y);    // sh = 0: t + o; sh = 1: o - t
+      });
+    } else {
+      sfor<0, R2>([&](auto kv) CPRA_INLINE {
+        constexpr int k = decltype(kv)::value;
+        C t = s0 ? twc<-1, k, R1>(g[k]) : g[k];              // W_R1^{s k}, s = s0 + 2 s1
+        t = s1 ? twc<-1, 2 * k, R1>(t) : t;
+        const C o1 = pair_lane<2 * PM, T>(t);                // across s1
+        const C u = s1 ? mk<C>(o1.x - t.x, o1.y - t.y) : mk<C>(t.x + o1.x, t.y + o1.y);
+        const C o0 = pair_lane<PM, T>(u);                    // across s0, W_4^{s1} on the odd half
+        const C wu = s1 ? mk<C>(u.y, -u.x) : u;              // W_4 = -i
+        const C wo = s1 ? mk<C>(o0.y, -o0.x) : o0;
+        g[k] = s0 ? mk<C>(o0.x - wu.x, o0.y - wu.y) : mk<C>(u.x + wo.x, u.y + wo.y);
+      });
+    }
     // modulus projection
     if (j0 != 0) {
       const bool neg = ((c + j) & 1) != 0;   // (-1)^(w + j), w = c + R2 (k + R2 sh), R2 even
@@ -844,13 +876,13 @@ __device__ __forceinline__ void col_pair_body(const cx<T>* __restrict__ P, cx<T>
       if (col == 0) {
         sfor<0, R2>([&](auto kv) CPRA_INLINE {
           constexpr int k = decltype(kv)::value;
-          zl[c + R2 * (k + R2 * sh)] = g[k];
+          zl[c + R2 * (k + R2 * mo)] = g[k];
         });
       }
       __syncthreads();
       sfor<0, R2>([&](auto kv) CPRA_INLINE {
         constexpr int k = decltype(kv)::value;
-        const int w = c + R2 * (k + R2 * sh);
+        const int w = c + R2 * (k + R2 * mo);
         if (j != 0) {
           const auto pa = AmpIO<AP>::load(An + pix<N>(w, j), as);
           g[k] = Proj<T>::template two<ERR>(g[k], (T)pa.x, (T)pa.y, ((w + j) & 1) != 0, scale, err, 1.0);
@@ -877,7 +909,7 @@ __device__ __forceinline__ void col_pair_body(const cx<T>* __restrict__ P, cx<T>
     };
     sfor<0, R2>([&](auto kv) CPRA_INLINE {
       constexpr int k = decltype(kv)::value;
-      const int w = c + R2 * (k + R2 * sh);
+      const int w = c + R2 * (k + R2 * mo);
       const int wm = wrapN<N>(N - w);
       C out;
       if (j != 0) {
@@ -902,9 +934,9 @@ __device__ __forceinline__ void col_pair_body(const cx<T>* __restrict__ P, cx<T>
     });
   }
 
-  // inverse: radix-2 butterfly across the lane pair, W_R1^{-sh k'}, R2-point IDFT over k'
+  // inverse: the S-point IDFT across the lanes, W_R1^{-sh k'}, R2-point IDFT over k'
   if constexpr (MODE == 0) __syncthreads();   // all forward reads of lds are done
-  {
+  if constexpr (SS == 2) {
     const T sgn = sh ? (T)-1 : (T)1;
     sfor<0, R2>([&](auto kv) CPRA_INLINE {
       constexpr int k = decltype(kv)::value;
@@ -912,16 +944,27 @@ __device__ __forceinline__ void col_pair_body(const cx<T>* __restrict__ P, cx<T>
       const C u = mk<C>(o.x + sgn * g[k].x, o.y + sgn * g[k].y);
       g[k] = sh ? twc<+1, k, R1>(u) : u;
     });
+  } else {
+    sfor<0, R2>([&](auto kv) CPRA_INLINE {
+      constexpr int k = decltype(kv)::value;
+      const C o0 = pair_lane<PM, T>(g[k]);                // across s0 (the lane holds m = s1 + 2 s0)
+      C u = s0 ? mk<C>(o0.x - g[k].x, o0.y - g[k].y) : mk<C>(g[k].x + o0.x, g[k].y + o0.y);
+      u = (s0 & s1) ? mk<C>(-u.y, u.x) : u;                 // W_4^{-s0 s1}: +i
+      const C o1 = pair_lane<2 * PM, T>(u);                 // across s1
+      C z = s1 ? mk<C>(o1.x - u.x, o1.y - u.y) : mk<C>(u.x + o1.x, u.y + o1.y);
+      z = s0 ? twc<+1, k, R1>(z) : z;                       // W_R1^{-s k'}, s = s0 + 2 s1
+      g[k] = s1 ? twc<+1, 2 * k, R1>(z) : z;
+    });
   }
-  dft<R2, +1>(g);   // g[a'] = Y'[c][sh + 2 a']
+  dft<R2, +1>(g);   // g[a'] = Y'[c][sh + S a']
   {
-    const C* ti = tw + TL::COLI + c * R1 + sh * R2;   // conj W_N^{(sh + 2a') c}
+    const C* ti = tw + TL::COLI + c * R1 + sh * R2;   // conj W_N^{(sh + S a') c}
     sfor<0, R2 / 2>([&](auto iv) CPRA_INLINE {
       constexpr int k = 2 * decltype(iv)::value;
       C t0, t1;
       load_pair(ti + k, t0, t1);
-      lds[c * LSTRIDE + (sh + 2 * k) * CC + col] = cmul(g[k], t0);
-      lds[c * LSTRIDE + (sh + 2 * (k + 1)) * CC + col] = cmul(g[k + 1], t1);
+      lds[c * LSTRIDE + (sh + SS * k) * CC + col] = cmul(g[k], t0);
+      lds[c * LSTRIDE + (sh + SS * (k + 1)) * CC + col] = cmul(g[k + 1], t1);
     });
   }
   __syncthreads();
