@@ -77,6 +77,7 @@ int col_tiles(int N) {
   }
 }
 
+// z-planes per step-D chunk: divides N and is a multiple of the gather's planes per thread
 int stepd_chunk(int N) { return N >= 384 ? 32 : N; }
 
 size_t mask_words_per_row(int N) {

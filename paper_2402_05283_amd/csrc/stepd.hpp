@@ -71,64 +71,72 @@ struct CellRec {
 constexpr int kStepdHeavy = 16;
 
 // Gather: Q_z[ky][kx] = (-1)^(ky+kx) / cnt(ky,kx) * sum over the cell's entries (n, u) of
-// (-1)^u S_n[z][u] (bilinear: weighted), one thread per cell, into the plane buffer.  No LDS, so
-// many waves are resident to hide the dependent loads.  A cell's entries are summed in CSR order,
-// their loads issued eight at a time (the cells near k = 0 hold many: the zero-frequency cell one
-// per angle).  1D grid of (N^2 / 256) * nz workgroups; XCD x (workgroup L mod 8) takes planes
-// [x nz/8, (x+1) nz/8) whole, so the staged rows those planes read stay in its L2.
+// (-1)^u S_n[z][u] (bilinear: weighted), into the plane buffer.  One thread per (cell, group of
+// kStepdZP planes): the cell's record and entry codes are read once for the group, and each entry
+// is one load per plane, all independent.  No LDS, so many waves are resident to hide the loads.
+// A cell's entries are summed in CSR order for every plane.  Heavy cells (first = -2) are left to
+// k_stepd_heavy.  1D grid of (N^2 / 256) * (nz / kStepdZP) workgroups; with 8 or more plane groups,
+// XCD x (workgroup L mod 8) takes groups [x G/8, (x+1) G/8) whole, so the staged rows those planes
+// read stay in its L2.
+constexpr int kStepdZP = 4;
 template <int N, typename T>
 __global__ void __launch_bounds__(256)
     k_stepd_gather(const cx<T>* __restrict__ Tz, int Np, const CellRec* __restrict__ cells,
                    const int* __restrict__ ent, const T* __restrict__ wts, const T* __restrict__ cnt_inv,
                    cx<T>* __restrict__ plane, int nz) {
   using C = cx<T>;
-  constexpr int H = N / 2, CBLK = N * N / 256;
+  constexpr int H = N / 2, CBLK = N * N / 256, ZP = kStepdZP;
+  const int G = nz / ZP;
   const int L = blockIdx.x;
-  int zi, cb;
-  if (nz % 8 == 0) {
+  int zg, cb;
+  if (G % 8 == 0) {
     const int x = L % 8, k = L / 8;
-    zi = x * (nz / 8) + k / CBLK;
+    zg = x * (G / 8) + k / CBLK;
     cb = k % CBLK;
   } else {
-    zi = L / CBLK;
+    zg = L / CBLK;
     cb = L % CBLK;
   }
   const int cell = cb * 256 + threadIdx.x;
   const int ky = cell / N, kx = cell % N;
-  const C* Tp = Tz + (size_t)zi * Np * H;   // this plane's rows of every angle
-  // (-1)^u S_n[z][u] from the packed row of angle n, without branches: S[u] = P[u] (u < N/2),
-  // conj P[N-u] (u > N/2), Re P[0] (u = 0), Im P[0] (u = N/2)
-  auto sample = [&](int e, int code) CPRA_INLINE -> C {
-    const int n = code / N, u = code % N;
-    const int j = u <= H ? (u == H ? 0 : u) : N - u;
-    const C p = Tp[(size_t)n * H + j];
-    T re = u == H ? p.y : p.x;
-    T im = (u == 0 || u == H) ? (T)0 : (u > H ? -p.y : p.y);
-    if (u & 1) { re = -re; im = -im; }
-    C s = mk<C>(re, im);
-    if (wts) s = cscale(s, wts[e]);      // bilinear insertion weight
-    return s;
-  };
   const CellRec rec = cells[cell];
   if (rec.first == -2) return;          // summed by k_stepd_heavy
-  C v = rec.first >= 0 ? sample(rec.begin, rec.first) : mk<C>((T)0, (T)0);
-  int e = rec.begin + 1;
-  for (; e + 8 <= rec.end; e += 8) {
-    int cd[8];
-    C sv[8];
+  const size_t pstride = (size_t)Np * H;   // one plane's rows of every angle
+  const C* Tp = Tz + (size_t)zg * ZP * pstride;
+  C v[ZP];
+  // v (first) or v + (-1)^u S_n[z][u] for the group's planes, from the packed rows of angle n:
+  // S[u] = P[u] (u < N/2), conj P[N-u] (u > N/2), Re P[0] (u = 0), Im P[0] (u = N/2)
+  auto take = [&](int e, int code, bool first) CPRA_INLINE {
+    const int n = code / N, u = code % N;
+    const int j = u <= H ? (u == H ? 0 : u) : N - u;
+    const C* src = Tp + (size_t)n * H + j;
+    C p[ZP];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) cd[q] = ent[e + q];
+    for (int z = 0; z < ZP; ++z) p[z] = src[(size_t)z * pstride];
+    const T w = wts ? wts[e] : (T)1;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sv[q] = sample(e + q, cd[q]);
+    for (int z = 0; z < ZP; ++z) {
+      T re = u == H ? p[z].y : p[z].x;
+      T im = (u == 0 || u == H) ? (T)0 : (u > H ? -p[z].y : p[z].y);
+      if (u & 1) { re = -re; im = -im; }
+      C sv = mk<C>(re, im);
+      if (wts) sv = cscale(sv, w);      // bilinear insertion weight
+      v[z] = first ? sv : cadd(v[z], sv);
+    }
+  };
+  if (rec.first >= 0) {
+    take(rec.begin, rec.first, true);
+  } else {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v = cadd(v, sv[q]);
+    for (int z = 0; z < ZP; ++z) v[z] = mk<C>((T)0, (T)0);
   }
-  for (; e < rec.end; ++e) v = cadd(v, sample(e, ent[e]));
+  for (int e = rec.begin + 1; e < rec.end; ++e) take(e, ent[e], false);
   T f;
   if constexpr (std::is_same<T, float>::value) f = __int_as_float(rec.inv_bits);
   else f = cnt_inv[cell];
   if ((ky + kx) & 1) f = -f;
-  plane[(size_t)zi * N * N + cell] = cscale(v, f);
+#pragma unroll
+  for (int z = 0; z < ZP; ++z) plane[(size_t)(zg * ZP + z) * N * N + cell] = cscale(v[z], f);
 }
 
 // The heavy cells of the gather: one wavefront per (heavy cell, plane), lane l summing entries
@@ -274,7 +282,8 @@ void stepd_run(const cx<T>* P, int Np, cx<T>* Tz, const CellRec* cells, const Ce
   for (int z0 = 0; z0 < N; z0 += zc) {
     const int nz = (N - z0) < zc ? (N - z0) : zc;
     k_stepd_stage<N, T><<<dim3(nz, Np), 256, 0, st>>>(P, Tz, z0, Np);
-    k_stepd_gather<N, T><<<(N * N / 256) * nz, 256, 0, st>>>(Tz, Np, cells, ent, wts, cnt_inv, plane, nz);
+    k_stepd_gather<N, T><<<(N * N / 256) * (nz / kStepdZP), 256, 0, st>>>(Tz, Np, cells, ent, wts, cnt_inv,
+                                                                          plane, nz);
     if (n_heavy > 0)
       k_stepd_heavy<N, T><<<dim3((n_heavy + 3) / 4, nz), 256, 0, st>>>(Tz, Np, heavy, n_heavy, ent, wts, cnt_inv,
                                                                         plane);
