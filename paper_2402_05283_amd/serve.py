@@ -16,7 +16,8 @@ cpra_iterate_batch (scans of one size share launches, size classes overlap on th
 are submitted without waiting for the GPU (the data check completes in stream order); at most
 `depth` episodes per scan are in flight, which bounds how long a frame submission can wait; a
 scan whose last frame has landed (its latency clock is running) may queue up to `depth_final` and
-is issued first, and with `hold_others` the other scans issue no new episode while such a scan is
+is issued first (it drains its backlog of frames and credit at once, up to that many episodes), and
+with `hold_others` the other scans issue no new episode while such a scan is
 unfinished, so it does not share the GPU with work whose latency is not yet being measured (the
 others fall behind their frames for that while and catch up afterwards; the logical schedule keeps
 their results unchanged).
@@ -153,13 +154,7 @@ class Server:
             self._retire_events(s)
             # submit the next frame only once the credit of the previous ones is spent
             if s.credit == 0 and s.arrived and s.n_submitted < s.n_expected:
-                n, I, S, _ = s.arrived.popleft()
-                with self.stream_ctx(s.plan):
-                    s.plan.submit(n, I, S, asynchronous=True)
-                s.n_submitted += 1
-                s.credit += self.r_frame + (self.r_final if s.n_submitted == s.n_expected else 0)
-                if s.n_submitted == s.n_expected:
-                    s.t_last_submit = self.clock()
+                self._submit_next(s)
                 progressed = True
         # a scan whose last frame has landed may queue more episodes (its latency is being
         # measured) and goes first in the batch; with hold_others the rest wait for it
@@ -177,12 +172,23 @@ class Server:
         if batch:
             self.batch_fn([s.plan for s in batch], self.n_ei)
             for s in batch:
-                s.credit -= self.n_ei
-                s.iters_done += self.n_ei
-                s.in_flight.append(self._record(s))
-                if s.credit == 0 and s.n_submitted == s.n_expected:
-                    s.t_last_issue = self.clock()
+                self._issued(s)
             progressed = True
+        # a scan on the clock drains its backlog now, up to depth_final episodes in flight: the next
+        # landed frame once its credit is spent, then that frame's episodes, and so on, instead of
+        # one frame and one episode per round
+        for s in self.active:
+            if not timed(s):
+                continue
+            while room(s) > 0:
+                if s.credit > 0:
+                    self.batch_fn([s.plan], self.n_ei)
+                    self._issued(s)
+                elif s.arrived and s.n_submitted < s.n_expected:
+                    self._submit_next(s)
+                else:
+                    break
+                progressed = True
         for s in list(self.active):
             if s.volume_event is None and s.n_submitted == s.n_expected and s.credit == 0:
                 with self.stream_ctx(s.plan):
@@ -201,6 +207,22 @@ class Server:
         if progressed:
             self._admit()
         return progressed
+
+    def _submit_next(self, s):
+        n, I, S, _ = s.arrived.popleft()
+        with self.stream_ctx(s.plan):
+            s.plan.submit(n, I, S, asynchronous=True)
+        s.n_submitted += 1
+        s.credit += self.r_frame + (self.r_final if s.n_submitted == s.n_expected else 0)
+        if s.n_submitted == s.n_expected:
+            s.t_last_submit = self.clock()
+
+    def _issued(self, s):
+        s.credit -= self.n_ei
+        s.iters_done += self.n_ei
+        s.in_flight.append(self._record(s))
+        if s.credit == 0 and s.n_submitted == s.n_expected:
+            s.t_last_issue = self.clock()
 
     @staticmethod
     def _record(s):

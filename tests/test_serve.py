@@ -138,7 +138,9 @@ def test_scans_on_the_clock_run_alone():
     def trace(hold):
         clock = FakeClock()
         log = []
-        srv = make_server(1 << 40, log, clock, n_ei=5, r_frame=5, r_final=20, hold_others=hold)
+        # depth_final 1: the timed scan takes one episode per round, so it stays unfinished for
+        # several rounds
+        srv = make_server(1 << 40, log, clock, n_ei=5, r_frame=5, r_final=20, depth_final=1, hold_others=hold)
         a = srv.open_scan(64, 2, seed=0)
         b = srv.open_scan(64, 6, seed=1)
         for n in range(2):
@@ -162,3 +164,23 @@ def test_scans_on_the_clock_run_alone():
     for sid in (0, 1):
         assert ops_of(log_h, sid) == ops_of(log_f, sid)
     assert a_h.volume == ("volume", 0, 2 * 5 + 20) and b_h.volume == ("volume", 1, 6 * 5 + 20)
+
+
+def test_scan_on_the_clock_queues_its_credit_at_once():
+    """A timed scan drains its backlog in one round: every landed frame is submitted and its credit
+    queued (up to depth_final episodes in flight), not one frame and one episode per round."""
+    class Pending:
+        def query(self):
+            return False
+
+    clock = FakeClock()
+    log = []
+    srv = make_server(1 << 40, log, clock, n_ei=5, r_frame=5, r_final=20, depth_final=8)
+    a = srv.open_scan(64, 2, seed=0)
+    for n in range(2):
+        srv.push_frame(a, n, None, None, t=0.0)
+    a.plan.record_event = lambda: Pending()          # nothing completes: in-flight work piles up
+    srv.step()
+    # one round submitted both frames and queued all their 2 * 5 + 20 iterations
+    assert a.n_submitted == 2 and a.credit == 0 and a.iters_done == 2 * 5 + 20
+    assert len(a.in_flight) == (2 * 5 + 20) // 5
