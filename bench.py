@@ -208,9 +208,9 @@ def summarize_pmc(fetch_dir, write_dir, cmd):
     out = {"source_sha256": kernel_source_hash(), "fetch_factor": ff, "write_factor": fw}
     lines = ["# HBM traffic of the column and row passes: N=512, Np=360 cell scan", "",
              "Commands (repo root, one MI355X; one counter per run):", "",
-             f"    {cmd.format(counter='FETCH_SIZE', out='pmc_fetch')}",
-             f"    {cmd.format(counter='WRITE_SIZE', out='pmc_write')}",
-             f"    python3 bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write", "",
+             f"    {cmd.format(counter='FETCH_SIZE', out=fetch_dir)}",
+             f"    {cmd.format(counter='WRITE_SIZE', out=write_dir)}",
+             f"    python3 bench.py --summarize-pmc {fetch_dir} {write_dir}", "",
              f"Calibration: a plain device copy of {COPY_BYTES >> 20} MiB reads "
              f"{sum(fetch['copy']) / len(fetch['copy']) / 2**20:.1f} MiB on FETCH_SIZE and "
              f"{sum(write['copy']) / len(write['copy']) / 2**20:.1f} MiB on WRITE_SIZE, so fetches are scaled "
@@ -810,20 +810,21 @@ def main():
     ap.add_argument("--summarize-sq", metavar="SQ_DIR", help="print the SQ-counter summary of a rocprofv3 --pmc run")
     args = ap.parse_args()
     if args.summarize_trace:
-        cmd = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace -o run "
+        tdir, tjson = args.summarize_trace
+        cmd = (f"rocprofv3 --kernel-trace --stats --output-format csv -d {tdir} -o run "
                "-- python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-compare --guesses 0 --serve-scans 0 --batch-scans 0 "
-               "--no-autotune > gpurun_out/trace_bench.json")
+               f"--no-autotune > {tjson}")
         print(summarize_trace(*args.summarize_trace, cmd), end="")
         return
     if args.summarize_sq:
         cmd = ("timeout -s KILL 180 rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU "
                "SQ_WAIT_INST_ANY SQ_INSTS_VMEM_RD SQ_INSTS_VALU SQ_WAIT_ANY GRBM_GUI_ACTIVE --output-format csv "
-               "-d gpurun_out/sq -o run -- python3 bench.py --steps 1 --warmup 0 --iters 20 --no-cpu-baseline "
+               f"-d {args.summarize_sq} -o run -- python3 bench.py --steps 1 --warmup 0 --iters 20 --no-cpu-baseline "
                "--serve-scans 0 --no-compare --guesses 0 --batch-scans 0 --no-autotune")
         print(summarize_sq(args.summarize_sq, cmd), end="")
         return
     if args.summarize_pmc:
-        cmd = ("timeout -s KILL 120 rocprofv3 --pmc {counter} --output-format csv -d gpurun_out/{out} -o run "
+        cmd = ("timeout -s KILL 120 rocprofv3 --pmc {counter} --output-format csv -d {out} -o run "
                "-- python3 bench.py --steps 1 --warmup 0 --iters 20 --no-cpu-baseline --serve-scans 0 --no-compare "
                "--guesses 0 --batch-scans 0 --no-autotune --calibrate-copy")
         print(summarize_pmc(*args.summarize_pmc, cmd), end="")
