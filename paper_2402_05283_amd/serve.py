@@ -20,7 +20,8 @@ is issued first (it drains its backlog of frames and credit at once, up to that 
 with `hold_others` the other scans issue no new episode while such a scan is
 unfinished, so it does not share the GPU with work whose latency is not yet being measured (the
 others fall behind their frames for that while and catch up afterwards; the logical schedule keeps
-their results unchanged).
+their results unchanged).  With `shortest_first`, of several scans on the clock the one with the
+least remaining work issues first.
 """
 from __future__ import annotations
 
@@ -68,8 +69,8 @@ class Server:
     """
 
     def __init__(self, hbm_budget, n_ei=10, r_frame=None, r_final=50, algo=_lib.HIO, beta=0.9, depth=1,
-                 depth_final=8, hold_others=True, clock=time.perf_counter, plan_factory=None, batch_fn=None,
-                 stream_ctx=None):
+                 depth_final=8, hold_others=True, shortest_first=True, clock=time.perf_counter, plan_factory=None,
+                 batch_fn=None, stream_ctx=None):
         r_frame = n_ei if r_frame is None else r_frame
         if r_frame % n_ei or r_final % n_ei or r_frame <= 0 or r_final < 0:
             raise ValueError("r_frame and r_final must be non-negative multiples of n_ei (r_frame > 0)")
@@ -77,6 +78,7 @@ class Server:
         self.n_ei, self.r_frame, self.r_final = n_ei, r_frame, r_final
         self.algo, self.beta, self.depth, self.depth_final = algo, beta, depth, max(depth, depth_final)
         self.hold_others = hold_others
+        self.shortest_first = shortest_first
         self.clock = clock
         self.plan_factory = plan_factory or self._make_plan
         self.batch_fn = batch_fn or (lambda plans, n: _lib.iterate_batch(plans, n, self.algo, self.beta))
@@ -162,9 +164,18 @@ class Server:
             return s.t_last_frame is not None
 
         hold = self.hold_others and any(timed(s) for s in self.active)
+        # shortest_first: of the scans on the clock with episodes still to issue, only the one with
+        # the least remaining work issues new ones (the others' queued episodes still run)
+        lead = None
+        if self.shortest_first:
+            ready = [s for s in self.active if timed(s) and (s.credit > 0 or s.arrived)]
+            if ready:
+                lead = min(ready, key=self._remaining)
 
         def room(s):
             if timed(s):
+                if lead is not None and s is not lead:
+                    return 0
                 return self.depth_final - len(s.in_flight)
             return 0 if hold else self.depth - len(s.in_flight)
         batch = [s for s in self.active if s.credit > 0 and room(s) > 0]
@@ -207,6 +218,12 @@ class Server:
         if progressed:
             self._admit()
         return progressed
+
+    def _remaining(self, s):
+        """Iterations still to issue times the pattern size and angle count: the scan's remaining GPU
+        work, up to a constant."""
+        left = s.credit + self.r_frame * len(s.arrived) + (self.r_final if s.n_submitted < s.n_expected else 0)
+        return left * s.N * s.N * s.n_expected
 
     def _submit_next(self, s):
         n, I, S, _ = s.arrived.popleft()

@@ -184,3 +184,36 @@ def test_scan_on_the_clock_queues_its_credit_at_once():
     # one round submitted both frames and queued all their 2 * 5 + 20 iterations
     assert a.n_submitted == 2 and a.credit == 0 and a.iters_done == 2 * 5 + 20
     assert len(a.in_flight) == (2 * 5 + 20) // 5
+
+
+def test_shortest_scan_on_the_clock_goes_first():
+    """Two scans on the clock: with shortest_first the one with less remaining work (smaller N) is
+    issued and finishes first, the other waits; without it both issue in the same rounds.  The
+    schedules (what each plan is asked to do) are the same either way."""
+    def trace(shortest):
+        clock = FakeClock()
+        log = []
+        srv = make_server(1 << 40, log, clock, n_ei=5, r_frame=5, r_final=10, depth_final=1,
+                          shortest_first=shortest)
+        big = srv.open_scan(128, 2, seed=0)
+        small = srv.open_scan(64, 2, seed=1)
+        for sc in (big, small):
+            for n in range(2):
+                srv.push_frame(sc, n, None, None, t=0.0)
+        order = []
+        while srv.busy():
+            clock.t += 1e-3
+            srv.step()
+            for sc in (big, small):
+                if sc.done and sc.sid not in order:
+                    order.append(sc.sid)
+        return log, order
+    log_s, order_s = trace(True)
+    log_f, order_f = trace(False)
+    assert order_s == [1, 0]
+    for sid in (0, 1):
+        assert ops_of(log_s, sid) == ops_of(log_f, sid)
+    # with shortest_first the big scan issues nothing until the small one has issued all of its work
+    first_small_done = max(i for i, e in enumerate(log_s) if e[0] == 1 and e[1] == "iterate")
+    big_iters_before = [e for e in log_s[:first_small_done] if e[0] == 0 and e[1] == "iterate"]
+    assert big_iters_before == []
