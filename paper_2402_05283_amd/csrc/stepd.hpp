@@ -65,9 +65,9 @@ struct CellRec {
 
 // Cells with more than kStepdHeavy entries (the cells near k = 0: the zero-frequency cell holds one
 // entry per angle) are left out of the per-cell gather, whose time is set by its longest chain of
-// dependent loads, and summed by k_stepd_heavy, one wavefront per (cell, plane).  Their records
-// carry first = -2 and an empty range; the heavy list holds their real records with first = the
-// cell index.
+// dependent loads, and summed by k_stepd_heavy, one wavefront per (cell, plane).  Their records in
+// the gather's table carry first = -2 (the gather skips them); the heavy list holds their real
+// records with first = the cell index.
 constexpr int kStepdHeavy = 16;
 
 // Gather: Q_z[ky][kx] = (-1)^(ky+kx) / cnt(ky,kx) * sum over the cell's entries (n, u) of
