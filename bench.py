@@ -160,6 +160,40 @@ def load_traffic():
     return None
 
 
+def roofline_of(col_ms, col_n, row_ms, row_n, n_it, amp_bytes=8, traffic=None):
+    """The roofline object of the N=512, Np=360 iteration from the HIP-event totals of the column and
+    row passes (col_ms over col_n launches, row_ms over row_n) across n_it timed iterations, and the
+    mean iteration time in ms.  A launch covers all 360 angles, or a chunk of them when the tuning
+    chose chunk-major order (then each pass takes several launches per iteration): algorithmic bytes
+    and counter traffic per launch are scaled by the angles a launch covers.  traffic: the counter
+    summary (load_traffic()), or None."""
+    col_b360, row_b360 = algorithmic_bytes(N, NP, N_EI, amp_bytes=amp_bytes)
+    per_launch = n_it / max(col_n, 1)          # fraction of the 360 angles one launch covers
+    col_b, row_b = col_b360 * per_launch, row_b360 * per_launch
+    col_avg = col_ms / max(col_n, 1)
+    row_avg = row_ms / max(row_n, 1)
+    col_gbs = col_b / (col_avg * 1e-3) / 1e9
+    row_gbs = row_b / (row_avg * 1e-3) / 1e9
+    dom = ("k_col", col_avg, col_gbs, col_b) if col_avg >= row_avg else ("k_row", row_avg, row_gbs, row_b)
+    traffic_b = round(traffic[dom[0]]["traffic_bytes"] * per_launch) if traffic else None
+    iter_ms = (col_ms + row_ms) / max(n_it, 1)
+    it_gbs = (col_b360 + row_b360) / (iter_ms * 1e-3) / 1e9
+    full_b = 46.525 * N * N * NP                # full-complex-spectrum byte model (two complex planes per pass)
+    other = ("k_row", row_avg, row_gbs) if dom[0] == "k_col" else ("k_col", col_avg, col_gbs)
+    roofline = {"bound": "hbm", "achieved": round(dom[2], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dom[2] / HBM_PEAK_GBS, 4), "traffic": traffic_b, "kernel": dom[0],
+                "avg_launch_ms": round(dom[1], 5), "bytes_per_launch": int(dom[3]),
+                "launches_per_iteration": round(1.0 / per_launch, 3),
+                "other": {"kernel": other[0], "avg_launch_ms": round(other[1], 5), "achieved": round(other[2], 1),
+                          "frac": round(other[2] / HBM_PEAK_GBS, 4)},
+                "fused_iteration": {"achieved": round(it_gbs, 1), "frac": round(it_gbs / HBM_PEAK_GBS, 4),
+                                    "bytes": int(col_b360 + row_b360), "ms": round(iter_ms, 5),
+                                    "what": "column + row pass algorithmic bytes over their summed mean "
+                                            "launch times: the whole fused FFT + projection iteration"},
+                "full_complex_model_frac": round(full_b / (iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return roofline, iter_ms
+
+
 def _pmc_rows(d):
     import csv
     import glob
@@ -909,35 +943,9 @@ def main():
     ms_per_step = total / args.steps * 1e3
     value = args.iters * NP * args.steps / total
 
-    # per-launch figures: a launch covers all 360 angles, or a chunk of them when the tuning chose
-    # chunk-major order (then each pass takes several launches per iteration)
-    col_b360, row_b360 = algorithmic_bytes(N, NP, N_EI, amp_bytes=4 if args.amp16 else 8)
-    n_it = args.iters * args.steps
-    per_launch = n_it / max(col_n, 1)          # fraction of the 360 angles one launch covers
-    col_b, row_b = col_b360 * per_launch, row_b360 * per_launch
-    col_avg = col_ms / max(col_n, 1)
-    row_avg = row_ms / max(row_n, 1)
-    col_gbs = col_b / (col_avg * 1e-3) / 1e9
-    row_gbs = row_b / (row_avg * 1e-3) / 1e9
-    dom = ("k_col", col_avg, col_gbs, col_b) if col_avg >= row_avg else ("k_row", row_avg, row_gbs, row_b)
     tr = load_traffic() if not args.amp16 else None
-    traffic = round(tr[dom[0]]["traffic_bytes"] * per_launch) if tr else None
-    iter_ms = (col_ms + row_ms) / max(n_it, 1)
-    it_gbs = (col_b360 + row_b360) / (iter_ms * 1e-3) / 1e9
-    full_b = 46.525 * N * N * NP                # full-complex-spectrum byte model (two complex planes per pass)
-    roofline = {"bound": "hbm", "achieved": round(dom[2], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dom[2] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom[0],
-                "avg_launch_ms": round(dom[1], 5), "bytes_per_launch": int(dom[3]),
-                "launches_per_iteration": round(1.0 / per_launch, 3),
-                "other": {"kernel": "k_row" if dom[0] == "k_col" else "k_col",
-                          "avg_launch_ms": round(row_avg if dom[0] == "k_col" else col_avg, 5),
-                          "achieved": round(row_gbs if dom[0] == "k_col" else col_gbs, 1),
-                          "frac": round((row_gbs if dom[0] == "k_col" else col_gbs) / HBM_PEAK_GBS, 4)},
-                "fused_iteration": {"achieved": round(it_gbs, 1), "frac": round(it_gbs / HBM_PEAK_GBS, 4),
-                                    "bytes": int(col_b360 + row_b360), "ms": round(iter_ms, 5),
-                                    "what": "column + row pass algorithmic bytes over their summed mean "
-                                            "launch times: the whole fused FFT + projection iteration"},
-                "full_complex_model_frac": round(full_b / (iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    roofline, iter_ms = roofline_of(col_ms, col_n, row_ms, row_n, args.iters * args.steps,
+                                    amp_bytes=4 if args.amp16 else 8, traffic=tr)
     out = {
         "metric": "pattern-iterations/s at N=512,N_p=360 + p99 last-frame-to-volume latency",
         "value": round(value, 1),
